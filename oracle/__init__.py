@@ -1,0 +1,198 @@
+"""GRIM-Filter oracle (test infrastructure only).
+
+A thin ctypes wrapper over ``oracle.c``, the plain CPU implementation of the
+bin-bitvector seed-location filter (Kim et al., BMC Genomics 2018, Sections
+"Genome Metadata Representation", "GRIM-Filter Operation" and "Taking Errors
+into Account").  Only the tests, the smoke check and the CPU-baseline leg of the
+benchmark may import this package; the product library never does.
+
+All sequences are numpy ``uint8`` arrays of base codes A=0 C=1 G=2 T=3.
+"""
+import ctypes
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+_lock = threading.Lock()
+
+_u8p = ctypes.POINTER(ctypes.c_uint8)
+_u32p = ctypes.POINTER(ctypes.c_uint32)
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+_i32p = ctypes.POINTER(ctypes.c_int32)
+
+
+def build(src=_SRC, out=_LIB):
+    """Compile oracle.c into a shared library with gcc (always recompiles)."""
+    tmp = out + ".tmp"
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-shared", "-fPIC",
+                           src, "-o", tmp])
+    os.replace(tmp, out)
+
+
+class Oracle:
+    """The oracle functions bound to one compiled copy of oracle.c."""
+
+    def __init__(self, path=_LIB):
+        lib = ctypes.CDLL(path)
+        u64, u32 = ctypes.c_uint64, ctypes.c_uint32
+        sig = {
+            "oracle_num_bins": (u64, [u64, u64]),
+            "oracle_vector_bytes": (u64, [u32]),
+            "oracle_token": (u64, [_u8p, u32]),
+            "oracle_build_bin": (None, [_u8p, u64, u64, u64, u32, u64, _u8p]),
+            "oracle_build_index": (None, [_u8p, u64, u64, u64, u32, u64, u64, _u8p]),
+            "oracle_max_edits": (u32, [u32, u32, u32]),
+            "oracle_num_tokens": (ctypes.c_int64, [u32, u32]),
+            "oracle_threshold": (ctypes.c_int64, [u32, u32, u32]),
+            "oracle_count": (ctypes.c_int32, [_u8p, u32, _u8p, u32]),
+            "oracle_filter": (u64, [_u8p, u64, u32, _u8p, _u64p, _u32p, _u32p, u32, u64, u64,
+                                    _u64p, _u32p, _i32p, _u8p]),
+            "oracle_pack_bitmask": (None, [_u8p, u64, _u32p]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+        self.lib = lib
+
+    def num_bins(self, G, B):
+        return int(self.lib.oracle_num_bins(G, B))
+
+    def vector_bytes(self, q):
+        return int(self.lib.oracle_vector_bytes(q))
+
+    def token(self, codes, q):
+        codes = _c(codes, np.uint8)
+        assert codes.size >= q
+        return int(self.lib.oracle_token(_ptr(codes, _u8p), q))
+
+    def max_edits(self, L, e_num, e_den):
+        return int(self.lib.oracle_max_edits(L, e_num, e_den))
+
+    def num_tokens(self, L, q):
+        return int(self.lib.oracle_num_tokens(L, q))
+
+    def threshold(self, L, q, E):
+        return int(self.lib.oracle_threshold(L, q, E))
+
+    def build_bin(self, ref, B, O, q, b):
+        ref = _c(ref, np.uint8)
+        vec = np.zeros(self.vector_bytes(q), dtype=np.uint8)
+        self.lib.oracle_build_bin(_ptr(ref, _u8p), ref.size, B, O, q, b, _ptr(vec, _u8p))
+        return vec
+
+    def build_index(self, ref, B, O, q, b_begin=0, b_end=None, n_threads=1):
+        """Bitvectors of bins [b_begin, b_end) as a (n, vector_bytes) uint8 array.
+
+        n_threads > 1 splits the bin range over Python threads (ctypes releases
+        the GIL); every thread runs the same plain per-bin routine."""
+        ref = _c(ref, np.uint8)
+        G = ref.size
+        if b_end is None:
+            b_end = self.num_bins(G, B)
+        nb = self.vector_bytes(q)
+        out = np.empty((b_end - b_begin, nb), dtype=np.uint8)
+        lib = self.lib
+
+        def work(lo, hi):
+            if hi > lo:
+                lib.oracle_build_index(_ptr(ref, _u8p), G, B, O, q, lo, hi,
+                                       ctypes.cast(out.ctypes.data + (lo - b_begin) * nb, _u8p))
+
+        _split(work, b_begin, b_end, n_threads)
+        return out
+
+    def count(self, vec, q, read):
+        vec = _c(vec, np.uint8)
+        read = _c(read, np.uint8)
+        return int(self.lib.oracle_count(_ptr(vec, _u8p), q, _ptr(read, _u8p), read.size))
+
+    def filter_batch(self, index, q, read_codes, read_off, read_len, read_e_num, e_den,
+                     cand_off, cand_bin, n_threads=1):
+        """Run the oracle filter over every read.
+
+        Returns (counts int32[n_pairs], pass uint8[n_pairs], n_out_of_range)."""
+        index = _c(index, np.uint8)
+        n_bins = index.shape[0] if index.ndim == 2 else index.size // self.vector_bytes(q)
+        read_codes = _c(read_codes, np.uint8)
+        read_off = _c(read_off, np.uint64)
+        read_len = _c(read_len, np.uint32)
+        read_e_num = _c(read_e_num, np.uint32)
+        cand_off = _c(cand_off, np.uint64)
+        cand_bin = _c(cand_bin, np.uint32)
+        n_reads = read_len.size
+        n_pairs = int(cand_off[-1]) if cand_off.size else 0
+        counts = np.empty(n_pairs, dtype=np.int32)
+        passed = np.empty(n_pairs, dtype=np.uint8)
+        lib = self.lib
+        bad = [0]
+        blk = threading.Lock()
+
+        def work(lo, hi):
+            if hi > lo:
+                n = lib.oracle_filter(_ptr(index, _u8p), n_bins, q, _ptr(read_codes, _u8p),
+                                      _ptr(read_off, _u64p), _ptr(read_len, _u32p),
+                                      _ptr(read_e_num, _u32p), e_den, lo, hi,
+                                      _ptr(cand_off, _u64p), _ptr(cand_bin, _u32p),
+                                      _ptr(counts, _i32p), _ptr(passed, _u8p))
+                with blk:
+                    bad[0] += int(n)
+
+        _split(work, 0, n_reads, n_threads)
+        return counts, passed, bad[0]
+
+    def pack_bitmask(self, passed):
+        passed = _c(passed, np.uint8)
+        words = np.zeros((passed.size + 31) // 32, dtype=np.uint32)
+        self.lib.oracle_pack_bitmask(_ptr(passed, _u8p), passed.size, _ptr(words, _u32p))
+        return words
+
+
+def _default():
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(_LIB):
+                build()
+            _lib = Oracle(_LIB)
+        return _lib
+
+
+def _ptr(a, t):
+    return a.ctypes.data_as(t)
+
+
+def _c(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _fwd(name):
+    def f(*args, **kw):
+        return getattr(_default(), name)(*args, **kw)
+    f.__name__ = name
+    f.__doc__ = getattr(Oracle, name).__doc__
+    return f
+
+
+for _n in ("num_bins", "vector_bytes", "token", "max_edits", "num_tokens", "threshold",
+           "build_bin", "build_index", "count", "filter_batch", "pack_bitmask"):
+    globals()[_n] = _fwd(_n)
+
+
+def _split(fn, lo, hi, n_threads):
+    n_threads = max(1, int(n_threads))
+    if n_threads == 1 or hi - lo < 2:
+        fn(lo, hi)
+        return
+    step = (hi - lo + n_threads - 1) // n_threads
+    ths = [threading.Thread(target=fn, args=(a, min(hi, a + step))) for a in range(lo, hi, step)]
+    for t in ths:
+        t.start()
+    for t in ths:
+        t.join()

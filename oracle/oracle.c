@@ -1,0 +1,193 @@
+/*
+ * GRIM-Filter oracle: a plain, slow, obviously correct CPU implementation of
+ * the bin-bitvector seed-location filter (Kim et al., "GRIM-Filter: Fast seed
+ * location filtering in DNA read mapping using processing-in-memory
+ * technologies", BMC Genomics 2018).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark may load this library.  The product path (the
+ * HIP library under paper_1711_01177_amd/) never calls, links or includes it,
+ * and this file shares no code, header, table or helper with that path.
+ *
+ * Inputs are unpacked base codes, one byte per base, A=0 C=1 G=2 T=3, exactly
+ * as the seeded generators emit them.  No 2-bit packing, no blocking, no
+ * deduplication, no reordering: every step follows the paper's description.
+ *
+ * Readings of points the paper leaves open (each is also listed in the design doc):
+ *   - token value: first base most significant, tok = sum_j code[j]*4^(q-1-j)
+ *   - bin b covers ref[b*B, min(G, (b+1)*B + O)); B is the stride, O the extra
+ *     overlap; only tokens lying wholly inside that range are recorded
+ *   - bit t of a bin vector is bit (t & 7) of byte (t >> 3)
+ *   - E = ceil(e*L) in exact integer arithmetic, e = e_num / e_den
+ *   - tokens of a read = max(0, L - q + 1); T = tokens - q*E (may be <= 0)
+ *   - the sum counts every token position of the read (multiplicity kept)
+ *   - pass iff sum >= T
+ *   - a candidate bin id >= n_bins yields count -1 and pass 0
+ *
+ * Every function cites the passage of the paper it follows.
+ */
+#include <stdint.h>
+#include <string.h>
+
+/* Number of bins: the genome is divided into consecutive bins of stride B
+ * (Section "Genome Metadata Representation"); the last one is truncated at G. */
+uint64_t oracle_num_bins(uint64_t G, uint64_t B)
+{
+    if (B == 0)
+        return 0;
+    return (G + B - 1) / B;
+}
+
+/* Bytes of one bin bitvector: 4^q existence bits, one per possible token
+ * (Section "Genome Metadata Representation"), rounded up to whole bytes. */
+uint64_t oracle_vector_bytes(uint32_t q)
+{
+    uint64_t bits = 1;
+    for (uint32_t j = 0; j < q; j++)
+        bits *= 4;
+    return (bits + 7) / 8;
+}
+
+/* Value of the token of length q starting at codes[0]: the q bases read as a
+ * base-4 number, first base most significant. */
+uint64_t oracle_token(const uint8_t *codes, uint32_t q)
+{
+    uint64_t t = 0;
+    for (uint32_t j = 0; j < q; j++)
+        t = t * 4 + codes[j];
+    return t;
+}
+
+/* Existence bitvector of bin b (Section "Genome Metadata Representation"):
+ * scan the bin's stretch of the genome and set the bit of every token found in
+ * it; all other bits stay 0.  Bins overlap so that a whole read fits into one
+ * bin (Section "GRIM-Filter Operation"): bin b spans [b*B, (b+1)*B + O),
+ * clipped to the genome.  vec receives oracle_vector_bytes(q) bytes. */
+void oracle_build_bin(const uint8_t *ref, uint64_t G, uint64_t B, uint64_t O,
+                      uint32_t q, uint64_t b, uint8_t *vec)
+{
+    uint64_t nbytes = oracle_vector_bytes(q);
+    memset(vec, 0, nbytes);
+    uint64_t lo = b * B;
+    uint64_t hi = (b + 1) * B + O;
+    if (hi > G)
+        hi = G;
+    if (lo >= hi)
+        return;
+    for (uint64_t p = lo; p + q <= hi; p++) {
+        uint64_t t = oracle_token(ref + p, q);
+        vec[t >> 3] |= (uint8_t)(1u << (t & 7));
+    }
+}
+
+/* Bitvectors of bins [b_begin, b_end), stored bin after bin (row b - b_begin
+ * of `index` holds bin b). */
+void oracle_build_index(const uint8_t *ref, uint64_t G, uint64_t B, uint64_t O,
+                        uint32_t q, uint64_t b_begin, uint64_t b_end,
+                        uint8_t *index)
+{
+    uint64_t nbytes = oracle_vector_bytes(q);
+    for (uint64_t b = b_begin; b < b_end; b++)
+        oracle_build_bin(ref, G, B, O, q, b, index + (b - b_begin) * nbytes);
+}
+
+/* Maximum number of tolerated errors: the ceiling of the read length times the
+ * error tolerance (Section "Taking Errors into Account"), with e = e_num/e_den
+ * kept as an exact fraction so that no binary rounding can move the ceiling. */
+uint32_t oracle_max_edits(uint32_t L, uint32_t e_num, uint32_t e_den)
+{
+    uint64_t num = (uint64_t)e_num * (uint64_t)L;
+    return (uint32_t)((num + e_den - 1) / e_den);
+}
+
+/* Number of tokens in a read of length L: L - (q - 1), none when L < q
+ * (Section "Taking Errors into Account"). */
+int64_t oracle_num_tokens(uint32_t L, uint32_t q)
+{
+    int64_t n = (int64_t)L - ((int64_t)q - 1);
+    return n > 0 ? n : 0;
+}
+
+/* Accumulation-sum threshold (Section "Taking Errors into Account", Fig. 5a):
+ * the read's token count minus q tokens for each of the E tolerated errors,
+ * every error assumed to destroy q tokens of its own. */
+int64_t oracle_threshold(uint32_t L, uint32_t q, uint32_t E)
+{
+    return oracle_num_tokens(L, q) - (int64_t)q * (int64_t)E;
+}
+
+/* Accumulation sum of one read against one bin bitvector (steps 1, 3 and 4 of
+ * Section "GRIM-Filter Operation"): extract every token of the read, look up
+ * its existence bit, add the bits up.  A token occurring k times in the read
+ * contributes k times, as in the all-A example of Section "Determining the
+ * Accumulation Sum Threshold". */
+int32_t oracle_count(const uint8_t *vec, uint32_t q, const uint8_t *read,
+                     uint32_t L)
+{
+    int64_t ntok = oracle_num_tokens(L, q);
+    int32_t sum = 0;
+    for (int64_t i = 0; i < ntok; i++) {
+        uint64_t t = oracle_token(read + i, q);          /* step 1 */
+        int bit = (vec[t >> 3] >> (t & 7)) & 1;          /* step 3 */
+        sum += bit;                                      /* step 4 */
+    }
+    return sum;
+}
+
+/* The filter over a batch (Sections "GRIM-Filter Operation" and "Integration
+ * with a Full Read Mapper"): for every read r in [r_begin, r_end) and every
+ * candidate bin of r, load the bin's bitvector (step 2), form the accumulation
+ * sum (steps 1, 3, 4), compare it with the threshold (step 5) and record the
+ * decision as one entry of the seed location filter bitmask, 1 = pass.
+ *
+ *   index       bitvectors of bins [0, n_bins), oracle_vector_bytes(q) each
+ *   read_codes  bases of all reads; read r is read_codes[read_off[r] ..+ read_len[r])
+ *   read_e_num  per-read error tolerance numerator; tolerance = read_e_num[r]/e_den
+ *   cand_off    CSR offsets: the candidates of read r are pairs
+ *               [cand_off[r], cand_off[r+1]) and their bins are cand_bin[pair]
+ *   counts      one int32 per pair (-1 for a bin id outside [0, n_bins))
+ *   pass        one byte per pair, 0 or 1
+ * Returns the number of pairs whose bin id was out of range. */
+uint64_t oracle_filter(const uint8_t *index, uint64_t n_bins, uint32_t q,
+                       const uint8_t *read_codes, const uint64_t *read_off,
+                       const uint32_t *read_len, const uint32_t *read_e_num,
+                       uint32_t e_den, uint64_t r_begin, uint64_t r_end,
+                       const uint64_t *cand_off, const uint32_t *cand_bin,
+                       int32_t *counts, uint8_t *pass)
+{
+    uint64_t nbytes = oracle_vector_bytes(q);
+    uint64_t bad = 0;
+    for (uint64_t r = r_begin; r < r_end; r++) {
+        const uint8_t *read = read_codes + read_off[r];
+        uint32_t L = read_len[r];
+        uint32_t E = oracle_max_edits(L, read_e_num[r], e_den);
+        int64_t T = oracle_threshold(L, q, E);
+        for (uint64_t k = cand_off[r]; k < cand_off[r + 1]; k++) {
+            uint64_t b = cand_bin[k];
+            if (b >= n_bins) {
+                counts[k] = -1;
+                pass[k] = 0;
+                bad++;
+                continue;
+            }
+            const uint8_t *vec = index + b * nbytes;     /* step 2 */
+            int32_t sum = oracle_count(vec, q, read, L);
+            counts[k] = sum;
+            pass[k] = (sum >= T) ? 1 : 0;                 /* step 5 */
+        }
+    }
+    return bad;
+}
+
+/* Seed location filter bitmask (Section "Integration with a Full Read
+ * Mapper"): one bit per location in input order; bit k is bit (k & 31) of
+ * 32-bit word (k >> 5).  words receives ceil(n / 32) words. */
+void oracle_pack_bitmask(const uint8_t *pass, uint64_t n, uint32_t *words)
+{
+    uint64_t nw = (n + 31) / 32;
+    for (uint64_t w = 0; w < nw; w++)
+        words[w] = 0;
+    for (uint64_t k = 0; k < n; k++)
+        if (pass[k])
+            words[k >> 5] |= 1u << (k & 31);
+}

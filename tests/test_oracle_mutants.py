@@ -1,0 +1,66 @@
+"""Planted-mistake check of the oracle's pins (CPU only).
+
+Each mutant is a copy of oracle/oracle.c with one plausible mistake (a dropped
+term, a wrong comparison, an off-by-one, a transposed index).  The copy is
+compiled into a temporary library and the pin suite must reject it.
+"""
+import os
+
+import pytest
+
+import oracle
+from tests import oracle_pins
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "oracle.c")
+
+MUTANTS = {
+    "token_base_order_reversed": ("t = t * 4 + codes[j];", "t = t * 4 + codes[q - 1 - j];"),
+    "bin_overlap_dropped": ("uint64_t hi = (b + 1) * B + O;", "uint64_t hi = (b + 1) * B;"),
+    "bin_start_shifted": ("uint64_t lo = b * B;", "uint64_t lo = b * B + 1;"),
+    "bin_last_token_dropped": ("for (uint64_t p = lo; p + q <= hi; p++)",
+                               "for (uint64_t p = lo; p + q < hi; p++)"),
+    "bit_order_within_byte": ("vec[t >> 3] |= (uint8_t)(1u << (t & 7));",
+                              "vec[t >> 3] |= (uint8_t)(1u << (7 - (t & 7)));"),
+    "edits_floor_not_ceil": ("return (uint32_t)((num + e_den - 1) / e_den);",
+                             "return (uint32_t)(num / e_den);"),
+    "edits_ceil_overshoot": ("return (uint32_t)((num + e_den - 1) / e_den);",
+                             "return (uint32_t)((num + e_den) / e_den);"),
+    "tokens_off_by_one": ("int64_t n = (int64_t)L - ((int64_t)q - 1);",
+                          "int64_t n = (int64_t)L - (int64_t)q;"),
+    "threshold_q_minus_one_per_error": ("return oracle_num_tokens(L, q) - (int64_t)q * (int64_t)E;",
+                                        "return oracle_num_tokens(L, q) - ((int64_t)q - 1) * (int64_t)E;"),
+    "threshold_sign": ("return oracle_num_tokens(L, q) - (int64_t)q * (int64_t)E;",
+                       "return oracle_num_tokens(L, q) + (int64_t)q * (int64_t)E;"),
+    "pass_strict_greater": ("pass[k] = (sum >= T) ? 1 : 0;", "pass[k] = (sum > T) ? 1 : 0;"),
+    "sum_drops_last_token": ("for (int64_t i = 0; i < ntok; i++) {",
+                             "for (int64_t i = 0; i + 1 < ntok; i++) {"),
+    "sum_ignores_repeats": ("sum += bit;                                      /* step 4 */",
+                            "if (i > 0 && t == oracle_token(read + i - 1, q)) bit = 0;\n"
+                            "        sum += bit;"),
+    "bins_floor": ("return (G + B - 1) / B;", "return G / B;"),
+    "bitmask_msb_first": ("words[k >> 5] |= 1u << (k & 31);",
+                          "words[k >> 5] |= 1u << (31 - (k & 31));"),
+    "bin_wrong_vector": ("const uint8_t *vec = index + b * nbytes;     /* step 2 */",
+                         "const uint8_t *vec = index + (b ^ 1) % n_bins * nbytes;"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_reject_mutant(name, tmp_path):
+    old, new = MUTANTS[name]
+    with open(SRC) as f:
+        text = f.read()
+    assert text.count(old) == 1, f"mutation site for {name} not found exactly once"
+    src = tmp_path / "oracle_mut.c"
+    src.write_text(text.replace(old, new))
+    lib = str(tmp_path / "liboracle_mut.so")
+    oracle.build(str(src), lib)
+    orc = oracle.Oracle(lib)
+    caught = []
+    for check in oracle_pins.ALL_CHECKS:
+        try:
+            check(orc)
+        except AssertionError:
+            caught.append(check.__name__)
+            break
+    assert caught, f"no pin rejects mutant {name}"
