@@ -1,0 +1,301 @@
+/*
+ * grim.h -- C ABI of the MI355X (gfx950) GRIM-Filter library.
+ *
+ * GRIM-Filter (Kim et al., "GRIM-Filter: Fast seed location filtering in DNA
+ * read mapping using processing-in-memory technologies", BMC Genomics 2018)
+ * decides, for every candidate location of a read, whether the location can be
+ * discarded before alignment.  The reference is cut into overlapping bins; each
+ * bin keeps a 4^q-bit existence vector of the q-grams ("tokens") it contains
+ * (Section "Genome Metadata Representation").  For a (read, bin) pair the
+ * accumulation sum is the number of the read's L - q + 1 token positions whose
+ * bit is set in the bin's vector, and the location passes iff the sum is at
+ * least T = (L - q + 1) - q * ceil(e * L) (Sections "GRIM-Filter Operation" and
+ * "Taking Errors into Account").  The mapper hands the library a read together
+ * with the candidate locations found by its seed lookup and receives one pass
+ * bit per location (Section "Integration with a Full Read Mapper").
+ *
+ * Conventions shared by every entry point:
+ *   - Base codes A=0 C=1 G=2 T=3.  Packed sequences hold 16 bases per 32-bit
+ *     word, base j of a word in bits [31-2j-1 .. 31-2j] (first base in the two
+ *     most significant bits); a base at stream position p lives in word p / 16.
+ *   - Token value: the q bases read as a base-4 number, first base most
+ *     significant.  Bit t of a bin vector is bit (t & 31) of 32-bit word t >> 5.
+ *   - Bin b covers reference positions [b*B, min(G, (b+1)*B + O)); only tokens
+ *     lying wholly inside are recorded.  n_bins = ceil(G / B).
+ *   - E = ceil(e * L) is computed exactly from e = e_num / e_den.  A read with
+ *     L < q has no tokens: its sum is 0 and it passes.
+ *   - Pass bit of pair k is bit (k & 31) of pass_bits[k >> 5].
+ *   - Every call returns GRIM_OK (0), GRIM_PENDING (> 0) or a negative error
+ *     code; no C++ exception crosses the ABI.  Pointers marked "device" must be
+ *     device memory of the GPU that is current on the calling thread.
+ *   - "stream" is a hipStream_t passed as void* (NULL = the null stream).
+ */
+#ifndef GRIM_H
+#define GRIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ return codes */
+#define GRIM_OK 0
+#define GRIM_PENDING 1            /* serving: the request is not finished yet   */
+#define GRIM_E_INVALID (-1)       /* bad argument, size or handle               */
+#define GRIM_E_BASE (-2)          /* a base outside A/C/G/T (or 0..3)           */
+#define GRIM_E_BIN_RANGE (-3)     /* a candidate bin id >= n_bins was seen      */
+#define GRIM_E_NOMEM (-4)         /* host or device allocation failed           */
+#define GRIM_E_BUDGET (-5)        /* serving: request larger than the budget    */
+#define GRIM_E_HIP (-6)           /* a HIP runtime call failed                  */
+#define GRIM_E_CANCELLED (-7)     /* serving: the request was cancelled         */
+#define GRIM_E_UNSUPPORTED (-8)   /* parameters outside what the kernels cover  */
+#define GRIM_E_IO (-9)            /* index file could not be read or written    */
+#define GRIM_E_TIMEOUT (-10)      /* serving: wait timed out                    */
+#define GRIM_E_READ (-11)         /* a read longer than max_len or outside the  */
+                                  /* packed buffer, or inconsistent cand_off    */
+
+/* Bits of the device status word that the filter kernels set. */
+#define GRIM_FLAG_BIN_RANGE 1u    /* some pair had bin id >= n_bins            */
+#define GRIM_FLAG_READ 2u         /* some read was invalid (see GRIM_E_READ)   */
+#define GRIM_FLAG_CAND_OFF 4u     /* cand_off was not a valid CSR offset array */
+
+/* Human-readable text of a return code (static storage, never NULL). */
+const char *grim_strerror(int code);
+
+/* Library version: major * 10000 + minor * 100 + patch. */
+int grim_version(void);
+
+/* ------------------------------------------------------------ host helpers */
+/* Number of 32-bit words grim_pack_bases writes for n bases: ceil(n / 16) plus
+ * one trailing zero word (kernels may read one word past a token's last base). */
+uint64_t grim_packed_words(uint64_t n_bases);
+
+/* Pack n bases (host memory) into the 2-bit layout above.  Accepts codes 0..3
+ * and the letters A C G T (either case).  words (host) receives
+ * grim_packed_words(n) words.  Any other byte: GRIM_E_BASE, words undefined.
+ * n_threads <= 0 uses all host cores. */
+int grim_pack_bases(const uint8_t *bases, uint64_t n, uint32_t *words, int n_threads);
+
+/* E = ceil(L * e_num / e_den), exactly (Section "Taking Errors into Account").
+ * e_den == 0: GRIM_E_INVALID. */
+int grim_max_edits(uint32_t L, uint32_t e_num, uint32_t e_den, uint32_t *E);
+
+/* T = max(0, L - q + 1) - q * E, the accumulation-sum threshold (same section). */
+int grim_threshold(uint32_t L, uint32_t q, uint32_t E, int64_t *T);
+
+/* ------------------------------------------------------------------- index */
+typedef struct grim_params {
+    uint32_t q;            /* token length: 4..7 (vectors of 32 B .. 2 KiB)     */
+    uint32_t reserved;     /* must be 0                                         */
+    uint64_t bin_stride;   /* B: bin b starts at b * B                          */
+    uint64_t overlap;      /* O: bin b extends O bases past (b+1) * B           */
+} grim_params_t;
+
+typedef struct grim_index grim_index_t; /* opaque, immutable once built */
+
+typedef struct grim_index_info {
+    uint32_t q;
+    int32_t device;           /* HIP device that holds the vectors               */
+    uint64_t bin_stride;
+    uint64_t overlap;
+    uint64_t genome_len;      /* G                                               */
+    uint64_t n_bins;
+    uint64_t vector_bytes;    /* 4^q / 8                                         */
+    uint64_t bytes;           /* n_bins * vector_bytes                           */
+    const void *vectors;      /* device: bin b at vectors + b * vector_bytes     */
+} grim_index_info_t;
+
+/* Build the bin vectors of a reference (Section "Genome Metadata
+ * Representation": scan the genome once and set the bit of every token of
+ * every bin).  ref_2bit: host, grim_packed_words(ref_len) words in the packed
+ * layout.  The vectors are built on the current device by a HIP kernel on
+ * `stream` and stay resident there; the call returns after the build has
+ * finished.  The caller owns *out and releases it with grim_index_free.
+ * Errors: GRIM_E_INVALID (NULL, ref_len == 0, B == 0, reserved != 0, more than
+ * 2^32 - 1 bins), GRIM_E_UNSUPPORTED (q outside 4..7), GRIM_E_NOMEM, GRIM_E_HIP. */
+int grim_build_bins(const uint32_t *ref_2bit, uint64_t ref_len, const grim_params_t *p,
+                    grim_index_t **out, void *stream);
+
+/* Describe an index. */
+int grim_index_info(const grim_index_t *idx, grim_index_info_t *out);
+
+/* Copy the vectors to host memory (host must hold info.bytes bytes). */
+int grim_index_copy_to_host(const grim_index_t *idx, void *host, uint64_t bytes);
+
+/* Store / reload an index: a 64-byte header (magic "GRIMIDX1", version, q, B,
+ * O, G, n_bins, FNV-1a checksum of the vectors) followed by the raw vectors.
+ * The paper keeps the bitvectors as genome metadata built once per reference
+ * (Section "Genome Metadata Representation").  load: GRIM_E_IO on a short,
+ * foreign or corrupt file. */
+int grim_index_save(const grim_index_t *idx, const char *path);
+int grim_index_load(const char *path, grim_index_t **out, void *stream);
+
+/* Release an index (NULL is ignored).  No filter call may be in flight on it. */
+void grim_index_free(grim_index_t *idx);
+
+/* ----------------------------------------------------------------- filtering */
+/* A batch of reads and their candidate locations (Section "Integration with a
+ * Full Read Mapper": the mapper sends each read with the seed locations its
+ * hash table returned).  All pointers are device pointers for grim_filter_*,
+ * host pointers for grim_serve_submit. */
+typedef struct grim_batch {
+    const uint32_t *reads_2bit;   /* packed bases of all reads                     */
+    uint64_t n_read_words;        /* words readable at reads_2bit                  */
+    const uint64_t *read_off;     /* [n_reads] stream position of each read's base 0 */
+    const uint32_t *read_len;     /* [n_reads] L                                   */
+    const uint32_t *read_e;       /* [n_reads] error tolerance numerator e_num     */
+    uint32_t e_den;               /* tolerance denominator (e.g. 10000), > 0       */
+    uint32_t max_len;             /* upper bound on every L, 1..8192               */
+    const uint64_t *cand_off;     /* [n_reads + 1] CSR offsets, cand_off[0] = 0,   */
+                                  /* non-decreasing, cand_off[n_reads] = n_pairs   */
+    const uint32_t *cand_bin;     /* [n_pairs] candidate bin ids (bin_num(z))      */
+    uint64_t n_reads;
+    uint64_t n_pairs;
+} grim_batch_t;
+
+/* Launch shape of the batched kernel.  Every choice computes identical
+ * results; only speed differs.  Zero fields take the default for the index's q. */
+typedef struct grim_tuning {
+    uint32_t lanes_per_cand;   /* lanes sharing one candidate's vector load       */
+    uint32_t unroll;           /* candidates in flight per lane group             */
+    uint32_t tile_pairs;       /* pairs per work-list tile (multiple of 64)       */
+    uint32_t wg_per_cu;        /* persistent workgroups per compute unit          */
+} grim_tuning_t;
+
+/* Fill *out with the default launch shape for token length q. */
+int grim_default_tuning(uint32_t q, grim_tuning_t *out);
+
+/* Launch shapes compiled for token length q: writes up to cap (lanes_per_cand,
+ * unroll) pairs into out (tile_pairs and wg_per_cu set to the defaults) and
+ * the number available into *n.  Use to enumerate or sweep shapes. */
+int grim_tuning_candidates(uint32_t q, grim_tuning_t *out, uint32_t cap, uint32_t *n);
+
+/* Device workspace (bytes) grim_filter_batch / grim_filter_plain need for a
+ * batch of n_pairs pairs with the given tuning (NULL = default). */
+int grim_workspace_size(const grim_index_t *idx, uint64_t n_pairs, const grim_tuning_t *tune,
+                        uint64_t *bytes);
+
+/* The filter, batched form: one persistent launch over the whole batch.
+ * A work-list kernel cuts the pair space into tiles and records the first read
+ * of each tile; the filter kernel's wavefronts pull tiles from an atomic
+ * counter.  For each pair it writes counts[k] (int32, the accumulation sum, or
+ * -1 for a bin id >= n_bins or an invalid read) and pass bit k (1 iff
+ * counts[k] >= T of the pair's read).  counts (device, n_pairs int32) and
+ * pass_bits (device, ceil(n_pairs / 32) words) are written in full.  workspace
+ * (device, >= grim_workspace_size bytes, 256-byte aligned) is owned by the
+ * caller and must not be shared by calls in flight at the same time.  The call
+ * is asynchronous on `stream`, allocates nothing and returns once the kernels
+ * are queued; problems found on the device are reported by grim_filter_status.
+ * Host-side errors: GRIM_E_INVALID, GRIM_E_UNSUPPORTED, GRIM_E_HIP. */
+int grim_filter_batch(const grim_index_t *idx, const grim_batch_t *b, int32_t *counts,
+                      uint32_t *pass_bits, void *workspace, uint64_t workspace_bytes,
+                      const grim_tuning_t *tune, void *stream);
+
+/* The same filter, plain form: one workgroup per read, no persistence, no
+ * tuning, no work list (the straightforward per-read launch the batched form
+ * is measured against).  Same arguments, outputs and errors. */
+int grim_filter_plain(const grim_index_t *idx, const grim_batch_t *b, int32_t *counts,
+                      uint32_t *pass_bits, void *workspace, uint64_t workspace_bytes,
+                      void *stream);
+
+/* Wait for `stream`, then read the status word the last filter call on this
+ * workspace left.  *flags (may be NULL) receives the GRIM_FLAG_* bits.
+ * Returns GRIM_OK, GRIM_E_BIN_RANGE, GRIM_E_READ or GRIM_E_HIP. */
+int grim_filter_status(const void *workspace, void *stream, uint32_t *flags);
+
+/* Pick the fastest launch shape for this index and a representative batch by
+ * timing each candidate shape on `stream` (outputs are overwritten).  The
+ * result is cached per (device, q, max_len) for later calls with tune = NULL. */
+int grim_tune(const grim_index_t *idx, const grim_batch_t *sample, int32_t *counts,
+              uint32_t *pass_bits, void *workspace, uint64_t workspace_bytes, void *stream,
+              grim_tuning_t *out);
+
+/* ---------------------------------------------------------------- HIP graphs */
+/* Capture the work-list and filter kernels of one grim_filter_batch call (same
+ * arguments, fixed buffers) into a HIP graph; replay it with grim_graph_launch
+ * on any stream.  The graph holds no memset nodes. */
+typedef struct grim_graph grim_graph_t;
+int grim_graph_create(const grim_index_t *idx, const grim_batch_t *b, int32_t *counts,
+                      uint32_t *pass_bits, void *workspace, uint64_t workspace_bytes,
+                      const grim_tuning_t *tune, grim_graph_t **out);
+int grim_graph_launch(grim_graph_t *g, void *stream);
+void grim_graph_destroy(grim_graph_t *g);
+
+/* ------------------------------------------------------------------ serving */
+/* A continuous-batching server over one resident index.  Requests (host
+ * batches) are copied at submit time; a scheduler thread admits queued
+ * requests while their device bytes fit in the HBM budget and a slot is free,
+ * fuses the admitted requests of one tick into a single batched launch on one
+ * of n_streams streams, and keeps admitting new requests while earlier ticks
+ * run.  Results are bit-identical to filtering each request alone.  Mirrors the
+ * overlap of filtering with the mapper's alignment through a bitmask buffer
+ * (Sections "Mapping GRIM-Filter to 3D-Stacked Memory with PIM" and "GRIM-Filter
+ * Parallelization"). */
+typedef struct grim_server grim_server_t;
+
+typedef struct grim_serve_cfg {
+    uint64_t hbm_budget_bytes;  /* device bytes for request buffers (0 = 1 GiB)     */
+    uint32_t max_inflight;      /* requests on the device at once (0 = 64)          */
+    uint32_t n_streams;         /* concurrent ticks (0 = 2)                         */
+    uint32_t max_tick_pairs;    /* pairs fused into one launch (0 = 64M)            */
+    uint32_t max_len;           /* longest read accepted (0 = 1024)                 */
+} grim_serve_cfg_t;
+
+typedef struct grim_req_stats {
+    double queue_ms;       /* submit -> admitted                                    */
+    double latency_ms;     /* submit -> results in host memory                      */
+    uint64_t n_pairs;
+    uint64_t tick;         /* which fused launch carried the request                */
+    uint32_t flags;        /* GRIM_FLAG_* bits seen in this request's pairs         */
+    int32_t status;        /* GRIM_OK, GRIM_E_BIN_RANGE, GRIM_E_READ, GRIM_E_CANCELLED */
+} grim_req_stats_t;
+
+typedef struct grim_serve_stats {
+    uint64_t submitted, completed, cancelled, failed, ticks;
+    uint64_t pairs_done;
+    double p50_ms, p99_ms, mean_ms, max_ms;  /* latency of completed requests      */
+    double busy_s;            /* wall time with at least one tick on the device     */
+    double pairs_per_s;       /* pairs_done / busy_s                                */
+    uint64_t peak_device_bytes;
+    double mean_requests_per_tick;
+} grim_serve_stats_t;
+
+/* Create a server on the current device.  It allocates its device pool
+ * (hbm_budget_bytes) and streams here, never on the request path. */
+int grim_serve_create(const grim_index_t *idx, const grim_serve_cfg_t *cfg, grim_server_t **out);
+
+/* Queue a request.  b holds HOST pointers; the arrays are copied before the call
+ * returns.  *ticket identifies the request.  Errors: GRIM_E_INVALID,
+ * GRIM_E_BUDGET (the request alone exceeds the budget), GRIM_E_NOMEM. */
+int grim_serve_submit(grim_server_t *s, const grim_batch_t *b, uint64_t *ticket);
+
+/* Non-blocking: GRIM_PENDING while the request runs; otherwise copies the
+ * results (host counts[n_pairs], pass_bits[ceil(n_pairs/32)]; either may be
+ * NULL), fills *st (may be NULL), forgets the ticket and returns the request's
+ * status.  Unknown ticket: GRIM_E_INVALID. */
+int grim_serve_poll(grim_server_t *s, uint64_t ticket, int32_t *counts, uint32_t *pass_bits,
+                    grim_req_stats_t *st);
+
+/* Blocking form of grim_serve_poll; timeout_ms < 0 waits forever.  Returns
+ * GRIM_E_TIMEOUT if the request is still running at the deadline. */
+int grim_serve_wait(grim_server_t *s, uint64_t ticket, int64_t timeout_ms, int32_t *counts,
+                    uint32_t *pass_bits, grim_req_stats_t *st);
+
+/* Cancel a request: a queued request never runs; a running one has its results
+ * dropped.  Its poll/wait then returns GRIM_E_CANCELLED. */
+int grim_serve_cancel(grim_server_t *s, uint64_t ticket);
+
+/* Aggregate statistics since creation (or the last reset). */
+int grim_serve_stats(grim_server_t *s, grim_serve_stats_t *out, int reset);
+
+/* Stop the scheduler (queued requests are cancelled, running ones finish) and
+ * free the server.  NULL is ignored. */
+void grim_serve_destroy(grim_server_t *s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GRIM_H */

@@ -1,0 +1,502 @@
+"""Python binding of the MI355X GRIM-Filter library (libgrim.so).
+
+Argument marshalling only: every step of the filter runs in the library's HIP
+kernels.  PyTorch provides device memory and the current HIP stream.  The
+functions keep the C ABI's names (include/grim.h); the few classes below own
+the opaque handles.  Importing works without a GPU; calling anything that
+touches the device needs one.  If libgrim.so has not been built the import
+raises, and nothing falls back to another implementation.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgrim.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1711_01177_amd.build` "
+                      "(or __graft_entry__.build())")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+GRIM_OK = 0
+GRIM_PENDING = 1
+GRIM_E_INVALID = -1
+GRIM_E_BASE = -2
+GRIM_E_BIN_RANGE = -3
+GRIM_E_NOMEM = -4
+GRIM_E_BUDGET = -5
+GRIM_E_HIP = -6
+GRIM_E_CANCELLED = -7
+GRIM_E_UNSUPPORTED = -8
+GRIM_E_IO = -9
+GRIM_E_TIMEOUT = -10
+GRIM_E_READ = -11
+GRIM_FLAG_BIN_RANGE = 1
+GRIM_FLAG_READ = 2
+GRIM_FLAG_CAND_OFF = 4
+
+_u8p = ctypes.POINTER(ctypes.c_uint8)
+_u32p = ctypes.POINTER(ctypes.c_uint32)
+_vp = ctypes.c_void_p
+_u64 = ctypes.c_uint64
+_u32 = ctypes.c_uint32
+
+
+class GrimError(RuntimeError):
+    def __init__(self, code, what=""):
+        self.code = code
+        super().__init__(f"{what}: {grim_strerror(code)} ({code})" if what else
+                         f"{grim_strerror(code)} ({code})")
+
+
+class grim_params_t(ctypes.Structure):
+    _fields_ = [("q", _u32), ("reserved", _u32), ("bin_stride", _u64), ("overlap", _u64)]
+
+
+class grim_index_info_t(ctypes.Structure):
+    _fields_ = [("q", _u32), ("device", ctypes.c_int32), ("bin_stride", _u64), ("overlap", _u64),
+                ("genome_len", _u64), ("n_bins", _u64), ("vector_bytes", _u64), ("bytes", _u64),
+                ("vectors", _vp)]
+
+
+class grim_batch_t(ctypes.Structure):
+    _fields_ = [("reads_2bit", _vp), ("n_read_words", _u64), ("read_off", _vp), ("read_len", _vp),
+                ("read_e", _vp), ("e_den", _u32), ("max_len", _u32), ("cand_off", _vp),
+                ("cand_bin", _vp), ("n_reads", _u64), ("n_pairs", _u64)]
+
+
+class grim_tuning_t(ctypes.Structure):
+    _fields_ = [("lanes_per_cand", _u32), ("unroll", _u32), ("tile_pairs", _u32),
+                ("wg_per_cu", _u32)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+class grim_serve_cfg_t(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", _u64), ("max_inflight", _u32), ("n_streams", _u32),
+                ("max_tick_pairs", _u32), ("max_len", _u32)]
+
+
+class grim_req_stats_t(ctypes.Structure):
+    _fields_ = [("queue_ms", ctypes.c_double), ("latency_ms", ctypes.c_double), ("n_pairs", _u64),
+                ("tick", _u64), ("flags", _u32), ("status", ctypes.c_int32)]
+
+
+class grim_serve_stats_t(ctypes.Structure):
+    _fields_ = [("submitted", _u64), ("completed", _u64), ("cancelled", _u64), ("failed", _u64),
+                ("ticks", _u64), ("pairs_done", _u64), ("p50_ms", ctypes.c_double),
+                ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
+                ("max_ms", ctypes.c_double), ("busy_s", ctypes.c_double),
+                ("pairs_per_s", ctypes.c_double), ("peak_device_bytes", _u64),
+                ("mean_requests_per_tick", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_P = ctypes.POINTER
+_SIGS = {
+    "grim_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "grim_version": (ctypes.c_int, []),
+    "grim_packed_words": (_u64, [_u64]),
+    "grim_pack_bases": (ctypes.c_int, [_vp, _u64, _vp, ctypes.c_int]),
+    "grim_max_edits": (ctypes.c_int, [_u32, _u32, _u32, _P(_u32)]),
+    "grim_threshold": (ctypes.c_int, [_u32, _u32, _u32, _P(ctypes.c_int64)]),
+    "grim_build_bins": (ctypes.c_int, [_vp, _u64, _P(grim_params_t), _P(_vp), _vp]),
+    "grim_index_info": (ctypes.c_int, [_vp, _P(grim_index_info_t)]),
+    "grim_index_copy_to_host": (ctypes.c_int, [_vp, _vp, _u64]),
+    "grim_index_save": (ctypes.c_int, [_vp, ctypes.c_char_p]),
+    "grim_index_load": (ctypes.c_int, [ctypes.c_char_p, _P(_vp), _vp]),
+    "grim_index_free": (None, [_vp]),
+    "grim_default_tuning": (ctypes.c_int, [_u32, _P(grim_tuning_t)]),
+    "grim_tuning_candidates": (ctypes.c_int, [_u32, _P(grim_tuning_t), _u32, _P(_u32)]),
+    "grim_workspace_size": (ctypes.c_int, [_vp, _u64, _P(grim_tuning_t), _P(_u64)]),
+    "grim_filter_batch": (ctypes.c_int, [_vp, _P(grim_batch_t), _vp, _vp, _vp, _u64,
+                                         _P(grim_tuning_t), _vp]),
+    "grim_filter_plain": (ctypes.c_int, [_vp, _P(grim_batch_t), _vp, _vp, _vp, _u64, _vp]),
+    "grim_filter_status": (ctypes.c_int, [_vp, _vp, _P(_u32)]),
+    "grim_tune": (ctypes.c_int, [_vp, _P(grim_batch_t), _vp, _vp, _vp, _u64, _vp,
+                                 _P(grim_tuning_t)]),
+    "grim_graph_create": (ctypes.c_int, [_vp, _P(grim_batch_t), _vp, _vp, _vp, _u64,
+                                         _P(grim_tuning_t), _P(_vp)]),
+    "grim_graph_launch": (ctypes.c_int, [_vp, _vp]),
+    "grim_graph_destroy": (None, [_vp]),
+    "grim_serve_create": (ctypes.c_int, [_vp, _P(grim_serve_cfg_t), _P(_vp)]),
+    "grim_serve_submit": (ctypes.c_int, [_vp, _P(grim_batch_t), _P(_u64)]),
+    "grim_serve_poll": (ctypes.c_int, [_vp, _u64, _vp, _vp, _P(grim_req_stats_t)]),
+    "grim_serve_wait": (ctypes.c_int, [_vp, _u64, ctypes.c_int64, _vp, _vp,
+                                       _P(grim_req_stats_t)]),
+    "grim_serve_cancel": (ctypes.c_int, [_vp, _u64]),
+    "grim_serve_stats": (ctypes.c_int, [_vp, _P(grim_serve_stats_t), ctypes.c_int]),
+    "grim_serve_destroy": (None, [_vp]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+EXPORTED = tuple(_SIGS)
+
+
+def grim_strerror(code):
+    return _lib.grim_strerror(int(code)).decode()
+
+
+def grim_version():
+    return int(_lib.grim_version())
+
+
+def _check(rc, what):
+    if rc != GRIM_OK:
+        raise GrimError(rc, what)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream=None):
+    if stream is not None:
+        return ctypes.c_void_p(int(stream))
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(int(t.data_ptr())) if t is not None else None
+
+
+# ------------------------------------------------------------------ host helpers
+def grim_packed_words(n_bases):
+    return int(_lib.grim_packed_words(int(n_bases)))
+
+
+def grim_pack_bases(bases, n_threads=0):
+    """Pack base codes (0..3) or ACGT letters (uint8 array) into 2-bit words."""
+    bases = np.ascontiguousarray(bases, dtype=np.uint8)
+    words = np.empty(grim_packed_words(bases.size), dtype=np.uint32)
+    _check(_lib.grim_pack_bases(bases.ctypes.data_as(_vp), bases.size,
+                                words.ctypes.data_as(_vp), int(n_threads)), "grim_pack_bases")
+    return words
+
+
+def grim_max_edits(L, e_num, e_den):
+    E = _u32()
+    _check(_lib.grim_max_edits(int(L), int(e_num), int(e_den), ctypes.byref(E)), "grim_max_edits")
+    return int(E.value)
+
+
+def grim_threshold(L, q, E):
+    T = ctypes.c_int64()
+    _check(_lib.grim_threshold(int(L), int(q), int(E), ctypes.byref(T)), "grim_threshold")
+    return int(T.value)
+
+
+def grim_default_tuning(q):
+    t = grim_tuning_t()
+    _check(_lib.grim_default_tuning(int(q), ctypes.byref(t)), "grim_default_tuning")
+    return t
+
+
+def grim_tuning_candidates(q):
+    """Launch shapes compiled for token length q, as grim_tuning_t list."""
+    n = _u32()
+    _check(_lib.grim_tuning_candidates(int(q), None, 0, ctypes.byref(n)), "grim_tuning_candidates")
+    arr = (grim_tuning_t * max(1, n.value))()
+    _check(_lib.grim_tuning_candidates(int(q), arr, n.value, ctypes.byref(n)),
+           "grim_tuning_candidates")
+    return [arr[i] for i in range(n.value)]
+
+
+def tuning(lanes_per_cand=0, unroll=0, tile_pairs=0, wg_per_cu=0):
+    return grim_tuning_t(lanes_per_cand, unroll, tile_pairs, wg_per_cu)
+
+
+# ------------------------------------------------------------------------ index
+class Index:
+    """A device-resident bin-vector index (owns a grim_index_t)."""
+
+    def __init__(self, handle):
+        self._h = ctypes.c_void_p(handle) if not isinstance(handle, ctypes.c_void_p) else handle
+        self.info = grim_index_info_t()
+        _check(_lib.grim_index_info(self._h, ctypes.byref(self.info)), "grim_index_info")
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def q(self):
+        return int(self.info.q)
+
+    @property
+    def n_bins(self):
+        return int(self.info.n_bins)
+
+    @property
+    def vector_bytes(self):
+        return int(self.info.vector_bytes)
+
+    @property
+    def bytes(self):
+        return int(self.info.bytes)
+
+    def to_host(self):
+        out = np.empty((self.n_bins, self.vector_bytes), dtype=np.uint8)
+        _check(_lib.grim_index_copy_to_host(self._h, out.ctypes.data_as(_vp), out.nbytes),
+               "grim_index_copy_to_host")
+        return out
+
+    def save(self, path):
+        _check(_lib.grim_index_save(self._h, str(path).encode()), "grim_index_save")
+
+    def free(self):
+        if self._h is not None and self._h.value:
+            _lib.grim_index_free(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def grim_build_bins(ref, q, bin_stride, overlap, stream=None, packed=False, ref_len=None):
+    """Build the index of a reference: codes/letters (uint8), or packed words
+    (uint32, with packed=True and ref_len given)."""
+    if packed:
+        words = np.ascontiguousarray(ref, dtype=np.uint32)
+        n = int(ref_len)
+        if words.size < grim_packed_words(n):
+            raise ValueError("packed reference shorter than grim_packed_words(ref_len)")
+    else:
+        words = grim_pack_bases(ref)
+        n = int(np.asarray(ref).size)
+    p = grim_params_t(int(q), 0, int(bin_stride), int(overlap))
+    h = ctypes.c_void_p()
+    _check(_lib.grim_build_bins(words.ctypes.data_as(_vp), n, ctypes.byref(p), ctypes.byref(h),
+                                _stream(stream)), "grim_build_bins")
+    return Index(h)
+
+
+def grim_index_load(path, stream=None):
+    h = ctypes.c_void_p()
+    _check(_lib.grim_index_load(str(path).encode(), ctypes.byref(h), _stream(stream)),
+           "grim_index_load")
+    return Index(h)
+
+
+# ------------------------------------------------------------------------ batch
+class Batch:
+    """Device copies of a batch (reads packed 2-bit, CSR candidates) and the
+    grim_batch_t that points at them."""
+
+    def __init__(self, codes, read_off, read_len, read_e, e_den, cand_off, cand_bin,
+                 max_len=None, device="cuda", words=None):
+        torch = _torch()
+        read_len = np.ascontiguousarray(read_len, dtype=np.uint32)
+        if words is None:
+            words = grim_pack_bases(codes)
+        words = np.ascontiguousarray(words, dtype=np.uint32)
+        self.n_reads = int(read_len.size)
+        cand_off = np.ascontiguousarray(cand_off, dtype=np.uint64)
+        self.n_pairs = int(cand_off[-1]) if cand_off.size else 0
+        if max_len is None:
+            max_len = max(1, int(read_len.max()) if read_len.size else 1)
+        self.max_len = int(max_len)
+        self.e_den = int(e_den)
+
+        def dev(a, dt):
+            a = np.ascontiguousarray(a)
+            if a.size == 0:
+                a = np.zeros(1, dtype=a.dtype)
+            return torch.from_numpy(a.view(dt)).to(device)
+
+        self.words = dev(words, np.int32)
+        self.read_off = dev(np.asarray(read_off, dtype=np.uint64), np.int64)
+        self.read_len = dev(read_len, np.int32)
+        self.read_e = dev(np.asarray(read_e, dtype=np.uint32), np.int32)
+        self.cand_off = dev(cand_off, np.int64)
+        self.cand_bin = dev(np.asarray(cand_bin, dtype=np.uint32), np.int32)
+        self.n_words = int(words.size)
+        self.c = grim_batch_t(_ptr(self.words), self.n_words, _ptr(self.read_off),
+                              _ptr(self.read_len), _ptr(self.read_e), self.e_den, self.max_len,
+                              _ptr(self.cand_off), _ptr(self.cand_bin), self.n_reads, self.n_pairs)
+
+    @classmethod
+    def from_workload(cls, w, device="cuda", max_len=None):
+        return cls(w["codes"], w["read_off"], w["read_len"], w["read_e"], w["e_den"],
+                   w["cand_off"], w["cand_bin"], max_len=max_len, device=device)
+
+
+def alloc_outputs(n_pairs, device="cuda"):
+    torch = _torch()
+    counts = torch.empty(max(1, n_pairs), dtype=torch.int32, device=device)
+    bits = torch.empty(max(1, (n_pairs + 31) // 32), dtype=torch.int32, device=device)
+    return counts, bits
+
+
+def grim_workspace_size(index, n_pairs, tune=None):
+    b = _u64()
+    _check(_lib.grim_workspace_size(index.handle, int(n_pairs),
+                                    ctypes.byref(tune) if tune is not None else None,
+                                    ctypes.byref(b)), "grim_workspace_size")
+    return int(b.value)
+
+
+def alloc_workspace(index, n_pairs, tune=None, device="cuda"):
+    torch = _torch()
+    nb = grim_workspace_size(index, n_pairs, tune)
+    ws = torch.empty(nb, dtype=torch.uint8, device=device)
+    if ws.data_ptr() % 256:
+        raise RuntimeError("workspace is not 256-byte aligned")
+    return ws
+
+
+def grim_filter_batch(index, batch, counts, pass_bits, workspace, tune=None, stream=None):
+    _check(_lib.grim_filter_batch(index.handle, ctypes.byref(batch.c), _ptr(counts),
+                                  _ptr(pass_bits), _ptr(workspace), workspace.numel(),
+                                  ctypes.byref(tune) if tune is not None else None,
+                                  _stream(stream)), "grim_filter_batch")
+
+
+def grim_filter_plain(index, batch, counts, pass_bits, workspace, stream=None):
+    _check(_lib.grim_filter_plain(index.handle, ctypes.byref(batch.c), _ptr(counts),
+                                  _ptr(pass_bits), _ptr(workspace), workspace.numel(),
+                                  _stream(stream)), "grim_filter_plain")
+
+
+def grim_filter_status(workspace, stream=None):
+    """Returns (code, flags) after waiting for the stream."""
+    f = _u32()
+    rc = _lib.grim_filter_status(_ptr(workspace), _stream(stream), ctypes.byref(f))
+    return int(rc), int(f.value)
+
+
+def grim_tune(index, batch, counts, pass_bits, workspace, stream=None):
+    t = grim_tuning_t()
+    _check(_lib.grim_tune(index.handle, ctypes.byref(batch.c), _ptr(counts), _ptr(pass_bits),
+                          _ptr(workspace), workspace.numel(), _stream(stream), ctypes.byref(t)),
+           "grim_tune")
+    return t
+
+
+class Graph:
+    """A captured work-list + filter launch (owns a grim_graph_t)."""
+
+    def __init__(self, index, batch, counts, pass_bits, workspace, tune=None):
+        self._h = ctypes.c_void_p()
+        self._keep = (index, batch, counts, pass_bits, workspace)
+        _check(_lib.grim_graph_create(index.handle, ctypes.byref(batch.c), _ptr(counts),
+                                      _ptr(pass_bits), _ptr(workspace), workspace.numel(),
+                                      ctypes.byref(tune) if tune is not None else None,
+                                      ctypes.byref(self._h)), "grim_graph_create")
+
+    def launch(self, stream=None):
+        _check(_lib.grim_graph_launch(self._h, _stream(stream)), "grim_graph_launch")
+
+    def destroy(self):
+        if self._h is not None and self._h.value:
+            _lib.grim_graph_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def grim_graph_create(index, batch, counts, pass_bits, workspace, tune=None):
+    return Graph(index, batch, counts, pass_bits, workspace, tune)
+
+
+# ---------------------------------------------------------------------- serving
+class HostBatch:
+    """Host arrays of one request and the grim_batch_t pointing at them."""
+
+    def __init__(self, codes, read_off, read_len, read_e, e_den, cand_off, cand_bin, max_len=None,
+                 words=None):
+        self.words = np.ascontiguousarray(words if words is not None else grim_pack_bases(codes),
+                                          dtype=np.uint32)
+        self.read_off = np.ascontiguousarray(read_off, dtype=np.uint64)
+        self.read_len = np.ascontiguousarray(read_len, dtype=np.uint32)
+        self.read_e = np.ascontiguousarray(read_e, dtype=np.uint32)
+        self.cand_off = np.ascontiguousarray(cand_off, dtype=np.uint64)
+        self.cand_bin = np.ascontiguousarray(cand_bin, dtype=np.uint32)
+        if self.cand_bin.size == 0:
+            self.cand_bin = np.zeros(1, dtype=np.uint32)
+        self.n_reads = int(self.read_len.size)
+        self.n_pairs = int(self.cand_off[-1]) if self.cand_off.size else 0
+        self.max_len = int(max_len if max_len is not None else
+                           (self.read_len.max() if self.read_len.size else 1))
+        self.c = grim_batch_t(self.words.ctypes.data, self.words.size, self.read_off.ctypes.data,
+                              self.read_len.ctypes.data, self.read_e.ctypes.data, int(e_den),
+                              self.max_len, self.cand_off.ctypes.data, self.cand_bin.ctypes.data,
+                              self.n_reads, self.n_pairs)
+
+
+class Server:
+    """Continuous-batching server over a resident index (owns a grim_server_t)."""
+
+    def __init__(self, index, hbm_budget_bytes=0, max_inflight=0, n_streams=0, max_tick_pairs=0,
+                 max_len=0):
+        self.index = index
+        cfg = grim_serve_cfg_t(int(hbm_budget_bytes), int(max_inflight), int(n_streams),
+                               int(max_tick_pairs), int(max_len))
+        self._h = ctypes.c_void_p()
+        _check(_lib.grim_serve_create(index.handle, ctypes.byref(cfg), ctypes.byref(self._h)),
+               "grim_serve_create")
+        self._pending = {}
+
+    def submit(self, hb):
+        t = _u64()
+        rc = _lib.grim_serve_submit(self._h, ctypes.byref(hb.c), ctypes.byref(t))
+        if rc != GRIM_OK:
+            raise GrimError(rc, "grim_serve_submit")
+        self._pending[int(t.value)] = hb.n_pairs
+        return int(t.value)
+
+    def _result(self, fn, ticket, *extra):
+        n = self._pending.get(ticket, 0)
+        counts = np.empty(max(1, n), dtype=np.int32)
+        bits = np.empty(max(1, (n + 31) // 32), dtype=np.uint32)
+        st = grim_req_stats_t()
+        rc = fn(self._h, int(ticket), *extra, counts.ctypes.data_as(_vp),
+                bits.ctypes.data_as(_vp), ctypes.byref(st))
+        if rc in (GRIM_PENDING, GRIM_E_TIMEOUT):
+            return rc, None, None, None
+        self._pending.pop(ticket, None)
+        return rc, counts[:n], bits[:(n + 31) // 32], st
+
+    def poll(self, ticket):
+        return self._result(_lib.grim_serve_poll, ticket)
+
+    def wait(self, ticket, timeout_ms=-1):
+        return self._result(lambda h, t, c, b, s: _lib.grim_serve_wait(h, t, int(timeout_ms), c, b, s),
+                            ticket)
+
+    def cancel(self, ticket):
+        _check(_lib.grim_serve_cancel(self._h, int(ticket)), "grim_serve_cancel")
+
+    def stats(self, reset=False):
+        s = grim_serve_stats_t()
+        _check(_lib.grim_serve_stats(self._h, ctypes.byref(s), int(bool(reset))), "grim_serve_stats")
+        return s.as_dict()
+
+    def destroy(self):
+        if self._h is not None and self._h.value:
+            _lib.grim_serve_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

@@ -1,0 +1,66 @@
+// Internal declarations shared by the GRIM-Filter kernels, the C ABI and the
+// serving runtime.  Not installed; the public interface is include/grim.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "grim.h"
+
+namespace grim {
+
+constexpr int kWave = 64;
+constexpr uint32_t kMaxLen = 8192;       // longest read the kernels accept
+constexpr uint64_t kWsHeader = 256;      // status word + tile counter, padded
+
+// Arguments of both filter kernels (passed by value).
+struct FilterArgs {
+    const uint4 *vec;           // bin vectors, 4^q / 8 bytes each
+    uint64_t n_bins;
+    const uint32_t *rw;         // packed reads
+    uint64_t nw;                // words readable at rw
+    const uint64_t *read_off;
+    const uint32_t *read_len;
+    const uint32_t *read_e;
+    uint32_t e_den;
+    uint32_t max_len;
+    const uint64_t *cand_off;
+    const uint32_t *cand_bin;
+    uint64_t n_reads;
+    uint64_t n_pairs;
+    int32_t *counts;
+    uint32_t *pass_bits;
+    uint32_t *status;
+    uint32_t *tile_counter;
+    const uint32_t *tile_read;
+    uint32_t n_tiles;
+    uint32_t tile_pairs;
+    int npl;                    // multiplicity planes reserved per read
+};
+
+struct BatchedVariant {
+    int q, g, u;
+    const void *kernel;
+};
+
+const BatchedVariant *batched_variants(int *n);
+const void *plain_kernel(int q);
+
+hipError_t launch_build(int q, dim3 grid, hipStream_t s, const uint32_t *ref, uint64_t nw,
+                        uint64_t G, uint64_t B, uint64_t O, uint64_t n_bins, uint32_t *out);
+hipError_t launch_worklist(hipStream_t s, const uint64_t *cand_off, uint64_t n_reads,
+                           uint32_t tile_pairs, uint32_t n_tiles, uint32_t *tile_read,
+                           uint32_t *status, uint32_t *counter);
+hipError_t launch_zero(hipStream_t s, uint32_t *p, uint64_t n);
+hipError_t launch_filter(const void *kernel, dim3 grid, dim3 block, size_t lds_bytes,
+                         hipStream_t s, const FilterArgs &a);
+
+}  // namespace grim
+
+// The index object behind the opaque grim_index_t handle.
+struct grim_index {
+    uint32_t q;
+    int device;
+    uint64_t B, O, G, n_bins, vector_bytes, bytes;
+    void *d_vec;
+};

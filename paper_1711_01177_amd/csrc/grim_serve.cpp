@@ -1,0 +1,721 @@
+// Continuous-batching server for GRIM-Filter requests.
+//
+// Requests are host batches (reads + candidate locations).  A scheduler thread
+// repeatedly (1) retires finished ticks, copying each request's slice of the
+// fused outputs back into its own result buffers, and (2) when a stream slot is
+// free, admits queued requests in arrival order while their device bytes fit in
+// what is left of the HBM budget, fuses them into one batch, and queues
+// H2D copy + batched filter launch + D2H copy on that slot's stream.  Ticks on
+// different streams overlap on the device, and requests that arrive while
+// ticks run join the next tick as soon as memory and a slot free up.
+//
+// Fusing only concatenates and re-bases offsets, and every pair is computed by
+// the same kernel from the same read and bin, so each request's counts and
+// pass bits are identical to filtering it alone.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "grim_internal.h"
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+inline uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
+
+double ms_between(Clock::time_point a, Clock::time_point b)
+{
+    return std::chrono::duration<double, std::milli>(b - a).count();
+}
+
+enum class State { Queued, Running, Done };
+
+struct Request {
+    uint64_t ticket = 0;
+    std::vector<uint32_t> words;
+    std::vector<uint64_t> read_off, cand_off;
+    std::vector<uint32_t> read_len, read_e, cand_bin;
+    uint32_t e_den = 0;
+    uint64_t n_reads = 0, n_pairs = 0;
+    std::vector<int32_t> counts;
+    std::vector<uint32_t> bits;
+    State state = State::Queued;
+    bool cancelled = false;
+    int status = GRIM_OK;
+    uint32_t flags = 0;
+    uint64_t tick = 0;
+    Clock::time_point t_submit, t_admit, t_done;
+};
+
+// Byte layout of one fused tick; the same offsets are used in the pinned
+// staging buffer and in the device chunk.
+struct Layout {
+    uint64_t words, read_off, read_len, read_e, cand_off, cand_bin;  // inputs
+    uint64_t in_bytes;
+    uint64_t counts, bits, out_bytes;  // outputs, relative to `out_base`
+    uint64_t out_base;
+    uint64_t ws, ws_bytes;
+    uint64_t total;
+};
+
+Layout plan(uint64_t n_words, uint64_t n_reads, uint64_t n_pairs, uint64_t ws_bytes)
+{
+    Layout L;
+    uint64_t o = 0;
+    L.words = o;
+    o = align256(o + n_words * 4);
+    L.read_off = o;
+    o = align256(o + n_reads * 8);
+    L.read_len = o;
+    o = align256(o + n_reads * 4);
+    L.read_e = o;
+    o = align256(o + n_reads * 4);
+    L.cand_off = o;
+    o = align256(o + (n_reads + 1) * 8);
+    L.cand_bin = o;
+    o = align256(o + n_pairs * 4);
+    L.in_bytes = o;
+    L.out_base = o;
+    L.counts = 0;
+    L.bits = align256(n_pairs * 4);
+    L.out_bytes = L.bits + align256(((n_pairs + 31) / 32) * 4 + 4);
+    o += L.out_bytes;
+    L.ws = o;
+    L.ws_bytes = align256(ws_bytes);
+    o += L.ws_bytes;
+    L.total = o;
+    return L;
+}
+
+// First-fit allocator over the server's device pool (offsets, 256-byte units).
+class Pool {
+public:
+    explicit Pool(uint64_t size) { free_[0] = size; }
+    bool alloc(uint64_t n, uint64_t *off)
+    {
+        n = align256(n);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= n) {
+                *off = it->first;
+                const uint64_t rest = it->second - n, start = it->first + n;
+                free_.erase(it);
+                if (rest)
+                    free_[start] = rest;
+                used_ += n;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(uint64_t off, uint64_t n)
+    {
+        n = align256(n);
+        used_ -= n;
+        auto it = free_.emplace(off, n).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    uint64_t used() const { return used_; }
+
+private:
+    std::map<uint64_t, uint64_t> free_;
+    uint64_t used_ = 0;
+};
+
+struct Slot {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    uint8_t *pinned = nullptr;
+    uint64_t pinned_bytes = 0;
+    bool busy = false;
+    // the tick in flight
+    std::vector<std::shared_ptr<Request>> reqs;
+    std::vector<uint64_t> pair_base;
+    Layout lay;
+    uint64_t dev_off = 0;
+    uint64_t tick = 0;
+    Clock::time_point t_launch;
+};
+
+}  // namespace
+
+struct grim_server {
+    const grim_index_t *idx = nullptr;
+    grim_serve_cfg_t cfg{};
+    int device = 0;
+    uint8_t *pool_base = nullptr;
+    std::unique_ptr<Pool> pool;
+    std::vector<Slot> slots;
+
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<std::shared_ptr<Request>> queue;
+    std::map<uint64_t, std::shared_ptr<Request>> all;
+    uint64_t next_ticket = 1, next_tick = 1;
+    uint64_t inflight_reqs = 0;
+    bool stop = false;
+    std::thread thr;
+
+    // statistics
+    uint64_t submitted = 0, completed = 0, cancelled = 0, failed = 0, ticks = 0, pairs_done = 0;
+    uint64_t reqs_in_ticks = 0, peak_bytes = 0;
+    std::vector<double> lat;
+    double busy_s = 0;
+    int running_ticks = 0;
+    Clock::time_point busy_since;
+
+    void run();
+    bool launch_tick(std::unique_lock<std::mutex> &lk);
+    void retire(Slot &s);
+};
+
+namespace {
+
+uint64_t ws_need(const grim_index_t *idx, uint64_t n_pairs)
+{
+    uint64_t b = 0;
+    grim_workspace_size(idx, n_pairs, nullptr, &b);
+    return b;
+}
+
+// Device bytes one request adds to a tick.
+uint64_t request_bytes(const Request &r)
+{
+    return align256(r.words.size() * 4) + align256(r.n_reads * 8) + 2 * align256(r.n_reads * 4) +
+           align256((r.n_reads + 1) * 8) + 2 * align256(r.n_pairs * 4) +
+           align256(((r.n_pairs + 31) / 32) * 4 + 4) + align256(4 * ((r.n_pairs + 511) / 512) + 64);
+}
+
+}  // namespace
+
+void grim_server::retire(Slot &s)
+{
+    // called with mu held, after s.done completed
+    const uint8_t *out = s.pinned + s.lay.out_base;
+    const int32_t *counts = reinterpret_cast<const int32_t *>(out + s.lay.counts);
+    const uint32_t *bits = reinterpret_cast<const uint32_t *>(out + s.lay.bits);
+    const auto now = Clock::now();
+    for (size_t j = 0; j < s.reqs.size(); ++j) {
+        Request &r = *s.reqs[j];
+        const uint64_t base = s.pair_base[j];
+        if (!r.cancelled) {
+            r.counts.assign(counts + base, counts + base + r.n_pairs);
+            const uint64_t nw = (r.n_pairs + 31) / 32;
+            r.bits.assign(nw, 0u);
+            const uint64_t w0 = base >> 5;
+            const uint32_t sh = (uint32_t)(base & 31);
+            for (uint64_t w = 0; w < nw; ++w) {
+                uint32_t x = bits[w0 + w] >> sh;
+                if (sh && (w0 + w + 1) * 32 < base + r.n_pairs)
+                    x |= bits[w0 + w + 1] << (32 - sh);
+                r.bits[w] = x;
+            }
+            if (r.n_pairs & 31)
+                r.bits[nw - 1] &= (1u << (r.n_pairs & 31)) - 1u;
+            bool bad = false;
+            for (uint64_t k = 0; k < r.n_pairs && !bad; ++k)
+                bad = r.counts[k] < 0;
+            r.flags = bad ? GRIM_FLAG_BIN_RANGE : 0u;
+            r.status = bad ? GRIM_E_BIN_RANGE : GRIM_OK;
+            if (bad)
+                ++failed;
+            ++completed;
+            pairs_done += r.n_pairs;
+            lat.push_back(ms_between(r.t_submit, now));
+        } else {
+            r.status = GRIM_E_CANCELLED;
+            ++cancelled;
+        }
+        r.t_done = now;
+        r.state = State::Done;
+        --inflight_reqs;
+    }
+    pool->release(s.dev_off, s.lay.total);
+    s.reqs.clear();
+    s.pair_base.clear();
+    s.busy = false;
+    if (--running_ticks == 0)
+        busy_s += std::chrono::duration<double>(now - busy_since).count();
+    cv_done.notify_all();
+}
+
+// Form and launch one tick on a free slot.  Returns false if nothing could be
+// launched.  Called with mu held; drops it while staging.
+bool grim_server::launch_tick(std::unique_lock<std::mutex> &lk)
+{
+    Slot *slot = nullptr;
+    for (auto &s : slots)
+        if (!s.busy) {
+            slot = &s;
+            break;
+        }
+    if (!slot)
+        return false;
+    while (!queue.empty() && queue.front()->cancelled) {
+        auto r = queue.front();
+        queue.pop_front();
+        r->status = GRIM_E_CANCELLED;
+        r->state = State::Done;
+        r->t_done = Clock::now();
+        ++cancelled;
+        cv_done.notify_all();
+    }
+    if (queue.empty())
+        return false;
+    // admission: FIFO prefix with the head's e_den, within slots, pairs, budget
+    std::vector<std::shared_ptr<Request>> take;
+    uint64_t words = 0, reads = 0, pairs = 0, bytes = 0;
+    const uint32_t e_den = queue.front()->e_den;
+    const uint64_t free_bytes = cfg.hbm_budget_bytes - pool->used();
+    for (auto it = queue.begin(); it != queue.end();) {
+        Request &r = **it;
+        if (r.cancelled) {
+            ++it;
+            continue;
+        }
+        if (r.e_den != e_den || inflight_reqs + take.size() >= cfg.max_inflight)
+            break;
+        if (!take.empty() && pairs + r.n_pairs > cfg.max_tick_pairs)
+            break;
+        const uint64_t nb = bytes + request_bytes(r);
+        const uint64_t total = plan(words + r.words.size() + 1, reads + r.n_reads,
+                                    pairs + r.n_pairs, ws_need(idx, pairs + r.n_pairs)).total;
+        if (total > free_bytes)
+            break;
+        take.push_back(*it);
+        words += r.words.size();
+        reads += r.n_reads;
+        pairs += r.n_pairs;
+        bytes = nb;
+        it = queue.erase(it);
+    }
+    if (take.empty())
+        return false;
+    Layout lay = plan(words + 1, reads, pairs, ws_need(idx, pairs));
+    uint64_t off = 0;
+    if (!pool->alloc(lay.total, &off)) {
+        // fragmented: put the requests back and wait for a tick to retire
+        for (auto it = take.rbegin(); it != take.rend(); ++it)
+            queue.push_front(*it);
+        return false;
+    }
+    peak_bytes = std::max(peak_bytes, pool->used());
+    const uint64_t tick = next_tick++;
+    const auto now = Clock::now();
+    for (auto &r : take) {
+        r->state = State::Running;
+        r->t_admit = now;
+        r->tick = tick;
+    }
+    inflight_reqs += take.size();
+    slot->busy = true;
+    slot->reqs = take;
+    slot->lay = lay;
+    slot->dev_off = off;
+    slot->tick = tick;
+    if (running_ticks++ == 0)
+        busy_since = now;
+    ++ticks;
+    reqs_in_ticks += take.size();
+
+    lk.unlock();
+    int rc = GRIM_OK;
+    // pinned staging buffer of this slot (grown rarely)
+    if (slot->pinned_bytes < lay.total) {
+        if (slot->pinned)
+            (void)hipHostFree(slot->pinned);
+        uint64_t nb = std::max<uint64_t>(lay.total, slot->pinned_bytes * 2);
+        if (hipHostMalloc(reinterpret_cast<void **>(&slot->pinned), nb, hipHostMallocDefault) !=
+            hipSuccess) {
+            slot->pinned = nullptr;
+            slot->pinned_bytes = 0;
+            rc = GRIM_E_NOMEM;
+        } else {
+            slot->pinned_bytes = nb;
+        }
+    }
+    slot->pair_base.clear();
+    if (rc == GRIM_OK) {
+        uint8_t *h = slot->pinned;
+        uint64_t wbase = 0, rbase = 0, pbase = 0;
+        uint64_t *coff = reinterpret_cast<uint64_t *>(h + lay.cand_off);
+        for (auto &rp : take) {
+            Request &r = *rp;
+            std::memcpy(h + lay.words + wbase * 4, r.words.data(), r.words.size() * 4);
+            uint64_t *ro = reinterpret_cast<uint64_t *>(h + lay.read_off) + rbase;
+            for (uint64_t i = 0; i < r.n_reads; ++i)
+                ro[i] = r.read_off[i] + wbase * 16;
+            std::memcpy(h + lay.read_len + rbase * 4, r.read_len.data(), r.n_reads * 4);
+            std::memcpy(h + lay.read_e + rbase * 4, r.read_e.data(), r.n_reads * 4);
+            for (uint64_t i = 0; i < r.n_reads; ++i)
+                coff[rbase + i] = r.cand_off[i] + pbase;
+            if (r.n_pairs)
+                std::memcpy(h + lay.cand_bin + pbase * 4, r.cand_bin.data(), r.n_pairs * 4);
+            slot->pair_base.push_back(pbase);
+            wbase += r.words.size();
+            rbase += r.n_reads;
+            pbase += r.n_pairs;
+        }
+        coff[rbase] = pbase;
+        reinterpret_cast<uint32_t *>(h + lay.words)[wbase] = 0u;
+        uint8_t *d = pool_base + off;
+        grim_batch_t b;
+        b.reads_2bit = reinterpret_cast<const uint32_t *>(d + lay.words);
+        b.n_read_words = wbase + 1;
+        b.read_off = reinterpret_cast<const uint64_t *>(d + lay.read_off);
+        b.read_len = reinterpret_cast<const uint32_t *>(d + lay.read_len);
+        b.read_e = reinterpret_cast<const uint32_t *>(d + lay.read_e);
+        b.e_den = e_den;
+        b.max_len = cfg.max_len;
+        b.cand_off = reinterpret_cast<const uint64_t *>(d + lay.cand_off);
+        b.cand_bin = reinterpret_cast<const uint32_t *>(d + lay.cand_bin);
+        b.n_reads = rbase;
+        b.n_pairs = pbase;
+        int32_t *dcounts = reinterpret_cast<int32_t *>(d + lay.out_base + lay.counts);
+        uint32_t *dbits = reinterpret_cast<uint32_t *>(d + lay.out_base + lay.bits);
+        if (hipMemcpyAsync(d, h, lay.in_bytes, hipMemcpyHostToDevice, slot->stream) != hipSuccess)
+            rc = GRIM_E_HIP;
+        if (rc == GRIM_OK)
+            rc = grim_filter_batch(idx, &b, dcounts, dbits, d + lay.ws, lay.ws_bytes, nullptr,
+                                   slot->stream);
+        if (rc == GRIM_OK &&
+            hipMemcpyAsync(h + lay.out_base, d + lay.out_base, lay.out_bytes, hipMemcpyDeviceToHost,
+                           slot->stream) != hipSuccess)
+            rc = GRIM_E_HIP;
+        if (rc == GRIM_OK && hipEventRecord(slot->done, slot->stream) != hipSuccess)
+            rc = GRIM_E_HIP;
+    }
+    slot->t_launch = Clock::now();
+    lk.lock();
+    if (rc != GRIM_OK) {
+        // the tick never reached the device: fail its requests
+        (void)hipStreamSynchronize(slot->stream);
+        const auto t = Clock::now();
+        for (auto &r : take) {
+            r->status = rc;
+            r->state = State::Done;
+            r->t_done = t;
+            ++failed;
+            --inflight_reqs;
+        }
+        pool->release(off, lay.total);
+        slot->reqs.clear();
+        slot->busy = false;
+        if (--running_ticks == 0)
+            busy_s += std::chrono::duration<double>(t - busy_since).count();
+        cv_done.notify_all();
+    }
+    return true;
+}
+
+void grim_server::run()
+{
+    (void)hipSetDevice(device);
+    std::unique_lock<std::mutex> lk(mu);
+    for (;;) {
+        bool progress = false;
+        for (auto &s : slots) {
+            if (s.busy && hipEventQuery(s.done) == hipSuccess) {
+                retire(s);
+                progress = true;
+            }
+        }
+        if (stop && running_ticks == 0)
+            break;
+        if (!stop)
+            while (launch_tick(lk))
+                progress = true;
+        if (!progress) {
+            if (running_ticks > 0)
+                cv_work.wait_for(lk, std::chrono::microseconds(50));
+            else
+                cv_work.wait_for(lk, std::chrono::milliseconds(5));
+        }
+    }
+}
+
+extern "C" int grim_serve_create(const grim_index_t *idx, const grim_serve_cfg_t *cfg,
+                                 grim_server_t **out)
+{
+    if (!idx || !out)
+        return GRIM_E_INVALID;
+    grim_serve_cfg_t c = cfg ? *cfg : grim_serve_cfg_t{};
+    if (!c.hbm_budget_bytes)
+        c.hbm_budget_bytes = 1ull << 30;
+    if (!c.max_inflight)
+        c.max_inflight = 64;
+    if (!c.n_streams)
+        c.n_streams = 2;
+    if (!c.max_tick_pairs)
+        c.max_tick_pairs = 64u << 20;
+    if (!c.max_len)
+        c.max_len = 1024;
+    if (c.max_len > grim::kMaxLen || c.n_streams > 16)
+        return GRIM_E_INVALID;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev != idx->device)
+        return GRIM_E_INVALID;
+    auto s = std::make_unique<grim_server>();
+    s->idx = idx;
+    s->cfg = c;
+    s->device = dev;
+    if (hipMalloc(reinterpret_cast<void **>(&s->pool_base), c.hbm_budget_bytes) != hipSuccess)
+        return GRIM_E_NOMEM;
+    s->pool = std::make_unique<Pool>(c.hbm_budget_bytes);
+    s->slots.resize(c.n_streams);
+    for (auto &sl : s->slots) {
+        if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess) {
+            for (auto &x : s->slots) {
+                if (x.stream)
+                    (void)hipStreamDestroy(x.stream);
+                if (x.done)
+                    (void)hipEventDestroy(x.done);
+            }
+            (void)hipFree(s->pool_base);
+            return GRIM_E_HIP;
+        }
+    }
+    grim_server *raw = s.release();
+    raw->thr = std::thread([raw] { raw->run(); });
+    *out = raw;
+    return GRIM_OK;
+}
+
+extern "C" int grim_serve_submit(grim_server_t *s, const grim_batch_t *b, uint64_t *ticket)
+{
+    if (!s || !b || !ticket || b->e_den == 0)
+        return GRIM_E_INVALID;
+    if (b->max_len > s->cfg.max_len)
+        return GRIM_E_UNSUPPORTED;
+    const uint64_t n = b->n_reads, P = b->n_pairs;
+    if ((n && (!b->read_off || !b->read_len || !b->read_e || !b->cand_off || !b->reads_2bit)) ||
+        (P && !b->cand_bin) || (!n && P))
+        return GRIM_E_INVALID;
+    auto r = std::make_shared<Request>();
+    try {
+        r->words.assign(b->reads_2bit, b->reads_2bit + (n ? b->n_read_words : 0));
+        r->read_off.assign(b->read_off, b->read_off + n);
+        r->read_len.assign(b->read_len, b->read_len + n);
+        r->read_e.assign(b->read_e, b->read_e + n);
+        if (n)
+            r->cand_off.assign(b->cand_off, b->cand_off + n + 1);
+        else
+            r->cand_off.assign(1, 0);
+        r->cand_bin.assign(b->cand_bin, b->cand_bin + P);
+    } catch (...) {
+        return GRIM_E_NOMEM;
+    }
+    // validate on the host: a request that is malformed never reaches the device
+    if (r->cand_off[0] != 0 || r->cand_off[n] != P)
+        return GRIM_E_INVALID;
+    const uint64_t nbases = (uint64_t)r->words.size() * 16;
+    for (uint64_t i = 0; i < n; ++i) {
+        if (r->cand_off[i + 1] < r->cand_off[i])
+            return GRIM_E_INVALID;
+        if (r->read_len[i] > b->max_len || r->read_off[i] > nbases ||
+            r->read_len[i] > nbases - r->read_off[i])
+            return GRIM_E_READ;
+    }
+    r->e_den = b->e_den;
+    r->n_reads = n;
+    r->n_pairs = P;
+    const uint64_t need = plan(r->words.size() + 1, n, P, ws_need(s->idx, P)).total;
+    if (need > s->cfg.hbm_budget_bytes)
+        return GRIM_E_BUDGET;
+    r->t_submit = Clock::now();
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (s->stop)
+            return GRIM_E_INVALID;
+        r->ticket = s->next_ticket++;
+        s->all[r->ticket] = r;
+        s->queue.push_back(r);
+        ++s->submitted;
+    }
+    s->cv_work.notify_one();
+    *ticket = r->ticket;
+    return GRIM_OK;
+}
+
+static int finish(grim_server_t *s, std::map<uint64_t, std::shared_ptr<Request>>::iterator it,
+                  int32_t *counts, uint32_t *pass_bits, grim_req_stats_t *st)
+{
+    Request &r = *it->second;
+    if (r.status == GRIM_OK || r.status == GRIM_E_BIN_RANGE) {
+        if (counts && !r.counts.empty())
+            std::memcpy(counts, r.counts.data(), r.counts.size() * 4);
+        if (pass_bits && !r.bits.empty())
+            std::memcpy(pass_bits, r.bits.data(), r.bits.size() * 4);
+    }
+    if (st) {
+        st->queue_ms = r.state == State::Done && r.t_admit.time_since_epoch().count()
+                           ? ms_between(r.t_submit, r.t_admit)
+                           : 0.0;
+        st->latency_ms = ms_between(r.t_submit, r.t_done);
+        st->n_pairs = r.n_pairs;
+        st->tick = r.tick;
+        st->flags = r.flags;
+        st->status = r.status;
+    }
+    const int rc = r.status;
+    s->all.erase(it);
+    return rc;
+}
+
+extern "C" int grim_serve_poll(grim_server_t *s, uint64_t ticket, int32_t *counts,
+                               uint32_t *pass_bits, grim_req_stats_t *st)
+{
+    if (!s)
+        return GRIM_E_INVALID;
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->all.find(ticket);
+    if (it == s->all.end())
+        return GRIM_E_INVALID;
+    if (it->second->state != State::Done)
+        return GRIM_PENDING;
+    return finish(s, it, counts, pass_bits, st);
+}
+
+extern "C" int grim_serve_wait(grim_server_t *s, uint64_t ticket, int64_t timeout_ms,
+                               int32_t *counts, uint32_t *pass_bits, grim_req_stats_t *st)
+{
+    if (!s)
+        return GRIM_E_INVALID;
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->all.find(ticket);
+    if (it == s->all.end())
+        return GRIM_E_INVALID;
+    auto req = it->second;
+    auto done = [&] { return req->state == State::Done; };
+    if (timeout_ms < 0)
+        s->cv_done.wait(lk, done);
+    else if (!s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), done))
+        return GRIM_E_TIMEOUT;
+    it = s->all.find(ticket);
+    if (it == s->all.end())
+        return GRIM_E_INVALID;
+    return finish(s, it, counts, pass_bits, st);
+}
+
+extern "C" int grim_serve_cancel(grim_server_t *s, uint64_t ticket)
+{
+    if (!s)
+        return GRIM_E_INVALID;
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->all.find(ticket);
+    if (it == s->all.end())
+        return GRIM_E_INVALID;
+    Request &r = *it->second;
+    if (r.state == State::Done)
+        return GRIM_OK;
+    r.cancelled = true;
+    if (r.state == State::Queued) {
+        for (auto q = s->queue.begin(); q != s->queue.end(); ++q)
+            if ((*q)->ticket == ticket) {
+                s->queue.erase(q);
+                break;
+            }
+        r.status = GRIM_E_CANCELLED;
+        r.state = State::Done;
+        r.t_done = Clock::now();
+        ++s->cancelled;
+        s->cv_done.notify_all();
+    }
+    return GRIM_OK;
+}
+
+extern "C" int grim_serve_stats(grim_server_t *s, grim_serve_stats_t *out, int reset)
+{
+    if (!s || !out)
+        return GRIM_E_INVALID;
+    std::lock_guard<std::mutex> lk(s->mu);
+    std::memset(out, 0, sizeof(*out));
+    out->submitted = s->submitted;
+    out->completed = s->completed;
+    out->cancelled = s->cancelled;
+    out->failed = s->failed;
+    out->ticks = s->ticks;
+    out->pairs_done = s->pairs_done;
+    std::vector<double> v = s->lat;
+    if (!v.empty()) {
+        std::sort(v.begin(), v.end());
+        auto pct = [&](double p) {
+            const size_t i = (size_t)std::min<double>(v.size() - 1, std::ceil(p * v.size()) - 1);
+            return v[i];
+        };
+        out->p50_ms = pct(0.50);
+        out->p99_ms = pct(0.99);
+        double sum = 0;
+        for (double x : v)
+            sum += x;
+        out->mean_ms = sum / v.size();
+        out->max_ms = v.back();
+    }
+    double busy = s->busy_s;
+    if (s->running_ticks > 0)
+        busy += std::chrono::duration<double>(Clock::now() - s->busy_since).count();
+    out->busy_s = busy;
+    out->pairs_per_s = busy > 0 ? s->pairs_done / busy : 0.0;
+    out->peak_device_bytes = s->peak_bytes;
+    out->mean_requests_per_tick = s->ticks ? (double)s->reqs_in_ticks / s->ticks : 0.0;
+    if (reset) {
+        s->submitted = s->completed = s->cancelled = s->failed = s->ticks = s->pairs_done = 0;
+        s->reqs_in_ticks = 0;
+        s->peak_bytes = s->pool->used();
+        s->lat.clear();
+        s->busy_s = 0;
+        if (s->running_ticks > 0)
+            s->busy_since = Clock::now();
+    }
+    return GRIM_OK;
+}
+
+extern "C" void grim_serve_destroy(grim_server_t *s)
+{
+    if (!s)
+        return;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+        for (auto &r : s->queue) {
+            r->status = GRIM_E_CANCELLED;
+            r->state = State::Done;
+        }
+        s->queue.clear();
+    }
+    s->cv_work.notify_all();
+    if (s->thr.joinable())
+        s->thr.join();
+    for (auto &sl : s->slots) {
+        (void)hipStreamSynchronize(sl.stream);
+        if (sl.pinned)
+            (void)hipHostFree(sl.pinned);
+        (void)hipEventDestroy(sl.done);
+        (void)hipStreamDestroy(sl.stream);
+    }
+    (void)hipFree(s->pool_base);
+    delete s;
+}
