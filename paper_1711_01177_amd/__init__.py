@@ -19,6 +19,15 @@ if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1711_01177_amd.build` "
                       "(or __graft_entry__.build())")
 
+# PyTorch ships its own HIP runtime under the same soname as the system one
+# (libamdhip64.so.7).  Loading torch first makes libgrim.so bind to that copy,
+# so the process holds a single HIP runtime and device pointers and streams
+# from torch are valid inside the library.
+try:
+    import torch as _torch_mod  # noqa: F401
+except ImportError:  # host-only use (packing, ABI checks) works without torch
+    _torch_mod = None
+
 _lib = ctypes.CDLL(LIB_PATH)
 
 GRIM_OK = 0

@@ -114,7 +114,7 @@ def test_edge_cases():
     add(ref[9000:9250], [45] * 100)                           # duplicate ids
     add(np.zeros(250, np.uint8), rng.integers(0, nb, 64))     # A^250: token multiplicity 246
     add(np.full(2000, 2, np.uint8), [0, 1, nb - 1])           # G^2000: multiplicity 1996
-    add(ref[20_000:21_000], [100, 101, 99, 5000])             # 1000 bp
+    add(ref[20_000:21_000], [100, 101, 99, nb - 2])           # 1000 bp
     add(ref[40_000:42_000], [200, 201, 202, 203, 9])          # 2000 bp
     for i in range(13):                                       # short tail reads
         add(ref[50_000 + i:50_000 + i + 17 + i], rng.integers(0, nb, i))
