@@ -148,12 +148,16 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-kernel comparison")
-    ap.add_argument("--tune", action="store_true", help="autotune the launch shape first")
+    ap.add_argument("--no-tune", action="store_true", help="use the default launch shape")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="time eager launches instead of HIP-graph replays (for counter runs)")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="run one device-to-device copy of this many MiB first (counter calibration)")
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--unroll", type=int, default=0)
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--wg", type=int, default=0)
-    ap.add_argument("--cpu-pairs", type=float, default=2.0e7)
+    ap.add_argument("--cpu-pairs", type=float, default=3.0e8)
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
     args = ap.parse_args()
 
@@ -193,7 +197,16 @@ def main():
     if args.lanes or args.unroll or args.tile or args.wg:
         tune = g.tuning(args.lanes, args.unroll, args.tile, args.wg)
     ws = g.alloc_workspace(idx, n_pairs, tune)
-    if args.tune:
+    if args.calibrate_copy_mib:
+        n = args.calibrate_copy_mib << 20
+        src = torch.ones(n, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy: {n} bytes")
+        del src, dst
+    if not args.no_tune and tune is None:
         t0 = time.time()
         tune = g.grim_tune(idx, batch, counts, bits, ws)
         log(f"[bench] tuned {tune.as_dict()} ({time.time() - t0:.1f}s)")
@@ -205,10 +218,17 @@ def main():
     if rc != 0:
         raise RuntimeError(f"filter status {rc} flags {flags}")
 
-    graph = g.grim_graph_create(idx, batch, counts, bits, ws, tune)
     stream = torch.cuda.current_stream()
+    if args.no_graph:
+        def step():
+            g.grim_filter_batch(idx, batch, counts, bits, ws, tune)
+    else:
+        graph = g.grim_graph_create(idx, batch, counts, bits, ws, tune)
+
+        def step():
+            graph.launch()
     for _ in range(args.warmup):
-        graph.launch()
+        step()
     torch.cuda.synchronize()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(args.steps)]
@@ -216,7 +236,7 @@ def main():
     t_wall = time.perf_counter()
     for e0, e1 in ev:
         e0.record(stream)
-        graph.launch()
+        step()
         e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_wall
@@ -225,7 +245,7 @@ def main():
     rc, flags = g.grim_filter_status(ws)
     if rc != 0:
         raise RuntimeError(f"filter status {rc} flags {flags}")
-    log(f"[bench] graph steps: mean {ms:.3f} ms  min {min(step_ms):.3f}  max {max(step_ms):.3f}  "
+    log(f"[bench] {'eager' if args.no_graph else 'graph'} steps: mean {ms:.3f} ms  min {min(step_ms):.3f}  max {max(step_ms):.3f}  "
         f"wall {wall * 1e3 / args.steps:.3f} ms/step")
 
     # eager launches (no graph) for comparison
@@ -291,11 +311,15 @@ def main():
 
     traffic = None
     try:
+        import hashlib
         with open(args.traffic_json) as f:
             tj = json.load(f)
-        key = f"{args.config}@{args.scale:g}"
-        if key in tj and tj[key].get("kernel_rev") == g.grim_version():
-            traffic = tj[key]["bytes_per_launch"]
+        rec = tj.get(f"{args.config}@{args.scale:g}")
+        with open(os.path.join(ROOT, "paper_1711_01177_amd", "csrc", "grim_kernels.hip"), "rb") as f:
+            src_hash = hashlib.sha1(f.read()).hexdigest()
+        shape = [eff.lanes_per_cand, eff.unroll, eff.tile_pairs, eff.wg_per_cu]
+        if rec and rec["kernel_source_sha1"] == src_hash and rec["tuning"] == shape:
+            traffic = rec["bytes_per_launch"]
     except (OSError, ValueError, KeyError):
         traffic = None
 
@@ -316,7 +340,9 @@ def main():
                                ("" if args.scale == 1.0 else f" (scaled x{args.scale:g})"),
                    "genome_bp": int(w["ref"].size), "n_reads": n_reads, "n_pairs": n_pairs,
                    "q": q, "bin_stride": w["B"], "overlap": w["O"], "n_bins": idx.n_bins,
-                   "index_bytes": idx.bytes, "tuning": eff.as_dict(), "hip_graph": True},
+                   "index_bytes": idx.bytes, "tuning": eff.as_dict(), "hip_graph": not args.no_graph,
+                   "autotuned": bool(not args.no_tune and not (args.lanes or args.unroll or
+                                                               args.tile or args.wg))},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "bytes_per_pair": bpp, "bytes_per_read": bpr,

@@ -206,7 +206,8 @@ int grim_filter_plain(const grim_index_t *idx, const grim_batch_t *b, int32_t *c
 int grim_filter_status(const void *workspace, void *stream, uint32_t *flags);
 
 /* Pick the fastest launch shape for this index and a representative batch by
- * timing each candidate shape on `stream` (outputs are overwritten).  The
+ * timing each candidate shape on `stream` over the batch's first 2^26 pairs at
+ * most (outputs of those pairs are overwritten).  The
  * result is cached per (device, q, max_len) for later calls with tune = NULL. */
 int grim_tune(const grim_index_t *idx, const grim_batch_t *sample, int32_t *counts,
               uint32_t *pass_bits, void *workspace, uint64_t workspace_bytes, void *stream,

@@ -515,7 +515,7 @@ extern "C" int grim_default_tuning(uint32_t q, grim_tuning_t *out)
     grim_tuning_t t = {0, 0, 1024, 8};
     switch (q) {
     case 4: t.lanes_per_cand = 2; t.unroll = 8; break;
-    case 5: t.lanes_per_cand = 8; t.unroll = 8; break;
+    case 5: t.lanes_per_cand = 4; t.unroll = 4; break;
     case 6: t.lanes_per_cand = 32; t.unroll = 4; break;
     case 7: t.lanes_per_cand = 64; t.unroll = 2; break;
     default: return GRIM_E_UNSUPPORTED;
@@ -627,6 +627,12 @@ extern "C" int grim_tune(const grim_index_t *idx, const grim_batch_t *sample, in
     if (!out)
         return GRIM_E_INVALID;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    // time on a prefix of the pair space (the kernel handles any prefix of a
+    // valid CSR batch): keeps a sweep over every shape to a few seconds
+    grim_batch_t sub = *sample;
+    if (sub.n_pairs > (1ull << 26))
+        sub.n_pairs = 1ull << 26;
+    sample = &sub;
     int nv = 0;
     const BatchedVariant *vars = batched_variants(&nv);
     const uint32_t tiles[] = {512, 1024, 2048};
