@@ -213,6 +213,23 @@ int grim_tune(const grim_index_t *idx, const grim_batch_t *sample, int32_t *coun
               uint32_t *pass_bits, void *workspace, uint64_t workspace_bytes, void *stream,
               grim_tuning_t *out);
 
+/* ------------------------------------------------------ seed location checker */
+/* The Seed Location Checker's first step (Section "Integration with a Full Read
+ * Mapper": it reads the seed location filter bitmask and passes on only the
+ * locations whose bit is set).  Compacts the pass bits of a filtered batch
+ * into the list of surviving locations, in input order:
+ *   surv_pair[i] (u64 pair index), surv_read[i] (u32 read), surv_bin[i] (u32 bin)
+ * for i < min(total, capacity); *n_survivors (device u64) receives the total,
+ * even when it exceeds capacity.  Only b->cand_off, b->cand_bin, b->n_reads and
+ * b->n_pairs are used.  Bits past n_pairs in the last word are ignored.
+ * workspace: device, >= grim_survivors_workspace_size bytes, 8-byte aligned.
+ * Asynchronous on `stream`; allocates nothing. */
+int grim_survivors_workspace_size(uint64_t n_pairs, uint64_t *bytes);
+int grim_compact_survivors(const grim_batch_t *b, const uint32_t *pass_bits, uint64_t capacity,
+                           uint64_t *surv_pair, uint32_t *surv_read, uint32_t *surv_bin,
+                           uint64_t *n_survivors, void *workspace, uint64_t workspace_bytes,
+                           void *stream);
+
 /* ---------------------------------------------------------------- HIP graphs */
 /* Capture the work-list and filter kernels of one grim_filter_batch call (same
  * arguments, fixed buffers) into a HIP graph; replay it with grim_graph_launch

@@ -54,6 +54,7 @@ class Oracle:
             "oracle_filter": (u64, [_u8p, u64, u32, _u8p, _u64p, _u32p, _u32p, u32, u64, u64,
                                     _u64p, _u32p, _i32p, _u8p]),
             "oracle_pack_bitmask": (None, [_u8p, u64, _u32p]),
+            "oracle_survivors": (u64, [_u32p, u64, _u64p, u64, _u32p, u64, _u64p, _u32p, _u32p]),
         }
         for name, (res, args) in sig.items():
             f = getattr(lib, name)
@@ -153,6 +154,21 @@ class Oracle:
         self.lib.oracle_pack_bitmask(_ptr(passed, _u8p), passed.size, _ptr(words, _u32p))
         return words
 
+    def survivors(self, words, n_pairs, cand_off, cand_bin):
+        """Passing locations in input order: (pair, read, bin) arrays."""
+        words = _c(words, np.uint32)
+        cand_off = _c(cand_off, np.uint64)
+        cand_bin = _c(cand_bin if len(cand_bin) else np.zeros(1, np.uint32), np.uint32)
+        n_reads = cand_off.size - 1
+        cap = int(n_pairs)
+        sp = np.empty(max(1, cap), dtype=np.uint64)
+        sr = np.empty(max(1, cap), dtype=np.uint32)
+        sb = np.empty(max(1, cap), dtype=np.uint32)
+        n = int(self.lib.oracle_survivors(_ptr(words, _u32p), int(n_pairs), _ptr(cand_off, _u64p),
+                                          n_reads, _ptr(cand_bin, _u32p), cap, _ptr(sp, _u64p),
+                                          _ptr(sr, _u32p), _ptr(sb, _u32p)))
+        return sp[:n], sr[:n], sb[:n]
+
 
 def _default():
     global _lib
@@ -181,7 +197,7 @@ def _fwd(name):
 
 
 for _n in ("num_bins", "vector_bytes", "token", "max_edits", "num_tokens", "threshold",
-           "build_bin", "build_index", "count", "filter_batch", "pack_bitmask"):
+           "build_bin", "build_index", "count", "filter_batch", "pack_bitmask", "survivors"):
     globals()[_n] = _fwd(_n)
 
 

@@ -191,3 +191,28 @@ void oracle_pack_bitmask(const uint8_t *pass, uint64_t n, uint32_t *words)
         if (pass[k])
             words[k >> 5] |= 1u << (k & 31);
 }
+
+/* Seed Location Checker, first step (Section "Integration with a Full Read
+ * Mapper"): read the seed location filter bitmask and list, in input order,
+ * every location whose bit is 1 -- its pair index, the read it belongs to and
+ * its bin.  Writes at most `capacity` entries; returns the number of passing
+ * locations. */
+uint64_t oracle_survivors(const uint32_t *words, uint64_t n_pairs, const uint64_t *cand_off,
+                          uint64_t n_reads, const uint32_t *cand_bin, uint64_t capacity,
+                          uint64_t *surv_pair, uint32_t *surv_read, uint32_t *surv_bin)
+{
+    uint64_t n = 0;
+    for (uint64_t r = 0; r < n_reads; r++) {
+        for (uint64_t k = cand_off[r]; k < cand_off[r + 1] && k < n_pairs; k++) {
+            if (!((words[k >> 5] >> (k & 31)) & 1u))
+                continue;
+            if (n < capacity) {
+                surv_pair[n] = k;
+                surv_read[n] = (uint32_t)r;
+                surv_bin[n] = cand_bin[k];
+            }
+            n++;
+        }
+    }
+    return n;
+}

@@ -130,6 +130,9 @@ _SIGS = {
     "grim_filter_status": (ctypes.c_int, [_vp, _vp, _P(_u32)]),
     "grim_tune": (ctypes.c_int, [_vp, _P(grim_batch_t), _vp, _vp, _vp, _u64, _vp,
                                  _P(grim_tuning_t)]),
+    "grim_survivors_workspace_size": (ctypes.c_int, [_u64, _P(_u64)]),
+    "grim_compact_survivors": (ctypes.c_int, [_P(grim_batch_t), _vp, _u64, _vp, _vp, _vp, _vp, _vp,
+                                              _u64, _vp]),
     "grim_graph_create": (ctypes.c_int, [_vp, _P(grim_batch_t), _vp, _vp, _vp, _u64,
                                          _P(grim_tuning_t), _P(_vp)]),
     "grim_graph_launch": (ctypes.c_int, [_vp, _vp]),
@@ -394,6 +397,28 @@ def grim_tune(index, batch, counts, pass_bits, workspace, stream=None):
                           _ptr(workspace), workspace.numel(), _stream(stream), ctypes.byref(t)),
            "grim_tune")
     return t
+
+
+def grim_compact_survivors(batch, pass_bits, capacity=None, stream=None):
+    """Survivor list of a filtered batch: (surv_pair, surv_read, surv_bin, n_total)
+    device tensors, truncated to min(total, capacity)."""
+    torch = _torch()
+    dev = pass_bits.device
+    cap = batch.n_pairs if capacity is None else int(capacity)
+    sp = torch.empty(max(1, cap), dtype=torch.int64, device=dev)
+    sr = torch.empty(max(1, cap), dtype=torch.int32, device=dev)
+    sb = torch.empty(max(1, cap), dtype=torch.int32, device=dev)
+    n = torch.zeros(1, dtype=torch.int64, device=dev)
+    nb = _u64()
+    _check(_lib.grim_survivors_workspace_size(batch.n_pairs, ctypes.byref(nb)),
+           "grim_survivors_workspace_size")
+    ws = torch.empty(int(nb.value), dtype=torch.uint8, device=dev)
+    _check(_lib.grim_compact_survivors(ctypes.byref(batch.c), _ptr(pass_bits), cap, _ptr(sp),
+                                       _ptr(sr), _ptr(sb), _ptr(n), _ptr(ws), ws.numel(),
+                                       _stream(stream)), "grim_compact_survivors")
+    total = int(n.item())
+    k = min(total, cap)
+    return sp[:k], sr[:k], sb[:k], total
 
 
 class Graph:

@@ -684,6 +684,38 @@ extern "C" int grim_tune(const grim_index_t *idx, const grim_batch_t *sample, in
     return GRIM_OK;
 }
 
+// ------------------------------------------------- seed location checker
+extern "C" int grim_survivors_workspace_size(uint64_t n_pairs, uint64_t *bytes)
+{
+    if (!bytes)
+        return GRIM_E_INVALID;
+    *bytes = (8 * std::max<uint64_t>(1, compact_blocks(n_pairs)) + 255) & ~255ull;
+    return GRIM_OK;
+}
+
+extern "C" int grim_compact_survivors(const grim_batch_t *b, const uint32_t *pass_bits,
+                                      uint64_t capacity, uint64_t *surv_pair, uint32_t *surv_read,
+                                      uint32_t *surv_bin, uint64_t *n_survivors, void *workspace,
+                                      uint64_t workspace_bytes, void *stream)
+{
+    if (!b || !n_survivors || !workspace)
+        return GRIM_E_INVALID;
+    if (b->n_reads == 0 && b->n_pairs != 0)
+        return GRIM_E_INVALID;
+    if (b->n_pairs && (!pass_bits || !b->cand_off || !b->cand_bin))
+        return GRIM_E_INVALID;
+    if (capacity && (!surv_pair || !surv_read || !surv_bin))
+        return GRIM_E_INVALID;
+    uint64_t need = 0;
+    grim_survivors_workspace_size(b->n_pairs, &need);
+    if (workspace_bytes < need || (reinterpret_cast<uintptr_t>(workspace) & 7))
+        return GRIM_E_INVALID;
+    HIP_TRY(launch_compact(reinterpret_cast<hipStream_t>(stream), pass_bits, b->n_pairs,
+                           b->cand_off, b->n_reads, b->cand_bin, capacity, surv_pair, surv_read,
+                           surv_bin, n_survivors, reinterpret_cast<uint64_t *>(workspace)));
+    return GRIM_OK;
+}
+
 // ---------------------------------------------------------------- graphs
 struct grim_graph {
     hipGraph_t graph;

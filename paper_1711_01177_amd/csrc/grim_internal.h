@@ -52,6 +52,11 @@ hipError_t launch_worklist(hipStream_t s, const uint64_t *cand_off, uint64_t n_r
                            uint32_t tile_pairs, uint32_t n_tiles, uint32_t *tile_read,
                            uint32_t *status, uint32_t *counter);
 hipError_t launch_zero(hipStream_t s, uint32_t *p, uint64_t n);
+hipError_t launch_compact(hipStream_t s, const uint32_t *bits, uint64_t n_pairs,
+                          const uint64_t *cand_off, uint64_t n_reads, const uint32_t *cand_bin,
+                          uint64_t cap, uint64_t *surv_pair, uint32_t *surv_read,
+                          uint32_t *surv_bin, uint64_t *n_out, uint64_t *block_sums);
+uint64_t compact_blocks(uint64_t n_pairs);
 hipError_t launch_filter(const void *kernel, dim3 grid, dim3 block, size_t lds_bytes,
                          hipStream_t s, const FilterArgs &a);
 

@@ -365,6 +365,22 @@ def check_bitmask_packing(orc):
     assert w.tolist() == [(1 << 0) | (1 << 5) | (1 << 31), (1 << 0) | (1 << 31), (1 << 0) | (1 << 5)]
 
 
+def check_survivor_list(orc):
+    """Seed Location Checker (Section 'Integration with a Full Read Mapper'): the
+    passing locations, in input order, with their read and bin -- hand example."""
+    passed = np.zeros(70, dtype=np.uint8)
+    passed[[0, 5, 31, 32, 63, 64, 69]] = 1
+    words = orc.pack_bitmask(passed)
+    cand_off = np.array([0, 3, 3, 40, 70], dtype=np.uint64)   # read 1 has no candidates
+    cand_bin = np.arange(70, dtype=np.uint32) * 3 + 1
+    sp, sr, sb = orc.survivors(words, 70, cand_off, cand_bin)
+    assert sp.tolist() == [0, 5, 31, 32, 63, 64, 69]
+    assert sr.tolist() == [0, 2, 2, 2, 3, 3, 3]
+    assert sb.tolist() == [1, 16, 94, 97, 190, 193, 208]
+    sp, sr, sb = orc.survivors(orc.pack_bitmask(np.zeros(70, np.uint8)), 70, cand_off, cand_bin)
+    assert sp.size == 0
+
+
 ALL_CHECKS = [
     check_golden_hand_vectors,
     check_all_a_example,
@@ -379,4 +395,5 @@ ALL_CHECKS = [
     check_footprint,
     check_edges,
     check_bitmask_packing,
+    check_survivor_list,
 ]

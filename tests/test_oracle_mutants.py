@@ -40,6 +40,8 @@ MUTANTS = {
     "bins_floor": ("return (G + B - 1) / B;", "return G / B;"),
     "bitmask_msb_first": ("words[k >> 5] |= 1u << (k & 31);",
                           "words[k >> 5] |= 1u << (31 - (k & 31));"),
+    "survivor_read_off_by_one": ("surv_read[n] = (uint32_t)r;", "surv_read[n] = (uint32_t)(r + 1);"),
+    "survivor_bit_inverted": ("if (!((words[k >> 5] >> (k & 31)) & 1u))", "if (((words[k >> 5] >> (k & 31)) & 1u))"),
     "bin_wrong_vector": ("const uint8_t *vec = index + b * nbytes;     /* step 2 */",
                          "const uint8_t *vec = index + (b ^ 1) % n_bins * nbytes;"),
 }
