@@ -188,7 +188,8 @@ def main():
     torch.cuda.synchronize()
     log(f"[bench] index: {idx.n_bins} bins, {idx.bytes / 1e9:.3f} GB ({time.time() - t0:.1f}s)")
     t0 = time.time()
-    batch = g.Batch.from_workload(w, max_len=int(w["read_len"].max()))
+    max_len_batch = int(w["read_len"].max())
+    batch = g.Batch.from_workload(w, max_len=max_len_batch)
     counts, bits = g.alloc_outputs(n_pairs)
     torch.cuda.synchronize()
     log(f"[bench] inputs resident ({time.time() - t0:.1f}s)")
@@ -299,6 +300,23 @@ def main():
                    pass_rate=total / max(1, n_pairs), algorithmic_gbs=cbytes / (cms * 1e-3) / 1e9,
                    note="timing includes the binding's small allocations and the total read-back")
     log(f"[bench] checker: {total} survivors in {cms:.3f} ms")
+    if max_len_batch <= 512:
+        idx.attach_reference(w["ref"])
+        dist, okb = g.grim_verify_survivors(idx, batch, sr, sb, total)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        g.grim_verify_survivors(idx, batch, sr, sb, total)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        vms = e0.elapsed_time(e1)
+        n_ok = int(torch.sum(torch.bitwise_and(
+            okb.view(torch.uint8).to(torch.int32)[:, None] >>
+            torch.arange(8, device="cuda", dtype=torch.int32)[None, :], 1)).item())
+        checker.update(verify_ms=vms, verified=n_ok,
+                       false_negative_rate=(total - n_ok) / max(1, total),
+                       verify_survivors_per_s=total / (vms * 1e-3))
+        log(f"[bench] alignment check: {n_ok}/{total} survivors within E edits, {vms:.3f} ms")
+        del dist, okb
     del sp, sr, sb
 
     check_n, check_bad = sample_check(w, counts, bits, 2000, rng)

@@ -230,6 +230,27 @@ int grim_compact_survivors(const grim_batch_t *b, const uint32_t *pass_bits, uin
                            uint64_t *n_survivors, void *workspace, uint64_t workspace_bytes,
                            void *stream);
 
+/* Keep a packed copy of the reference (host ref_2bit, grim_packed_words(ref_len)
+ * words; ref_len must equal the index's genome length) on the index's device,
+ * as grim_verify_survivors needs it.  Replaces an earlier copy. */
+int grim_index_attach_reference(grim_index_t *idx, const uint32_t *ref_2bit, uint64_t ref_len,
+                                void *stream);
+
+/* Alignment check of surviving locations -- the step the Seed Location Checker
+ * hands the survivors to (Section "Integration with a Full Read Mapper").  For
+ * survivor i (read surv_read[i], bin surv_bin[i]): d = the smallest edit
+ * distance (unit substitutions, insertions, deletions) between the read and
+ * any substring of the bin's span [b*B, min(G, (b+1)*B + O)).  Writes
+ * dist[i] = min(d, E + 1) with E = ceil(e * L) of that read, and sets bit i of
+ * ok_bits iff d <= E.  dist[i] = -1 (bit clear) for a read or bin id out of
+ * range.  Needs grim_index_attach_reference first (else GRIM_E_INVALID) and
+ * b->max_len <= 512 (else GRIM_E_UNSUPPORTED).  surv_*, dist (n_survivors
+ * int32) and ok_bits (ceil(n_survivors / 32) words) are device memory;
+ * asynchronous on `stream`, allocates nothing. */
+int grim_verify_survivors(const grim_index_t *idx, const grim_batch_t *b,
+                          const uint32_t *surv_read, const uint32_t *surv_bin,
+                          uint64_t n_survivors, int32_t *dist, uint32_t *ok_bits, void *stream);
+
 /* ---------------------------------------------------------------- HIP graphs */
 /* Capture the work-list and filter kernels of one grim_filter_batch call (same
  * arguments, fixed buffers) into a HIP graph; replay it with grim_graph_launch

@@ -54,6 +54,8 @@ class Oracle:
             "oracle_filter": (u64, [_u8p, u64, u32, _u8p, _u64p, _u32p, _u32p, u32, u64, u64,
                                     _u64p, _u32p, _i32p, _u8p]),
             "oracle_pack_bitmask": (None, [_u8p, u64, _u32p]),
+            "oracle_edit_distance_in_bin": (ctypes.c_int32, [_u8p, u64, u64, u64, u64, _u8p, u32,
+                                                             _i32p]),
             "oracle_survivors": (u64, [_u32p, u64, _u64p, u64, _u32p, u64, _u64p, _u32p, _u32p]),
         }
         for name, (res, args) in sig.items():
@@ -169,6 +171,28 @@ class Oracle:
                                           _ptr(sr, _u32p), _ptr(sb, _u32p)))
         return sp[:n], sr[:n], sb[:n]
 
+    def edit_distance_in_bin(self, ref, B, O, b, read):
+        """Smallest edit distance between `read` and any substring of bin b's span."""
+        ref = _c(ref, np.uint8)
+        L = len(read)
+        read = _c(read if L else np.zeros(1, np.uint8), np.uint8)
+        lo = b * B
+        hi = min(ref.size, (b + 1) * B + O)
+        row = np.empty(max(1, hi - lo + 1), dtype=np.int32)
+        return int(self.lib.oracle_edit_distance_in_bin(_ptr(ref, _u8p), ref.size, B, O, b,
+                                                        _ptr(read, _u8p), L, _ptr(row, _i32p)))
+
+    def verify(self, ref, B, O, read_codes, read_off, read_len, read_e, e_den, surv_read,
+               surv_bin):
+        """Distances capped at E + 1 and verified flags for a survivor list."""
+        d = np.empty(len(surv_read), dtype=np.int32)
+        for i, (r, b) in enumerate(zip(surv_read, surv_bin)):
+            o, L = int(read_off[r]), int(read_len[r])
+            E = self.max_edits(L, int(read_e[r]), e_den)
+            dist = self.edit_distance_in_bin(ref, B, O, int(b), read_codes[o:o + L])
+            d[i] = min(dist, E + 1)
+        return d
+
 
 def _default():
     global _lib
@@ -197,7 +221,8 @@ def _fwd(name):
 
 
 for _n in ("num_bins", "vector_bytes", "token", "max_edits", "num_tokens", "threshold",
-           "build_bin", "build_index", "count", "filter_batch", "pack_bitmask", "survivors"):
+           "build_bin", "build_index", "count", "filter_batch", "pack_bitmask", "survivors",
+           "edit_distance_in_bin", "verify"):
     globals()[_n] = _fwd(_n)
 
 

@@ -216,3 +216,46 @@ uint64_t oracle_survivors(const uint32_t *words, uint64_t n_pairs, const uint64_
     }
     return n;
 }
+
+/* Alignment check of one surviving location, the work the Seed Location
+ * Checker hands to the aligner (Section "Integration with a Full Read
+ * Mapper"): the smallest edit distance (substitutions, insertions, deletions,
+ * each cost 1) between the read and any substring of the bin's span
+ * [b*B, min(G, (b+1)*B + O)).  Plain dynamic programming with a free start and
+ * end in the reference (Sellers' approximate-matching recurrence):
+ *   D[0][j] = 0,  D[i][0] = i,
+ *   D[i][j] = min(D[i-1][j] + 1, D[i][j-1] + 1, D[i-1][j-1] + (read[i-1] != ref[j-1])),
+ * answer = min_j D[L][j].  `row` must hold (hi - lo + 1) int32 of scratch. */
+int32_t oracle_edit_distance_in_bin(const uint8_t *ref, uint64_t G, uint64_t B, uint64_t O,
+                                    uint64_t b, const uint8_t *read, uint32_t L, int32_t *row)
+{
+    uint64_t lo = B * b;               /* the bin's span, as in oracle_build_bin */
+    uint64_t hi = B * (b + 1) + O;
+    if (hi > G)
+        hi = G;
+    if (lo > hi)
+        lo = hi;
+    uint64_t n = hi - lo;
+    for (uint64_t j = 0; j <= n; j++)
+        row[j] = 0;                                   /* D[0][j] = 0 */
+    for (uint32_t i = 1; i <= L; i++) {
+        int32_t diag = row[0];                        /* D[i-1][0] */
+        row[0] = (int32_t)i;                          /* D[i][0] = i */
+        for (uint64_t j = 1; j <= n; j++) {
+            int32_t up = row[j];                      /* D[i-1][j] */
+            int32_t best = up + 1;
+            if (row[j - 1] + 1 < best)                /* D[i][j-1] + 1 */
+                best = row[j - 1] + 1;
+            int32_t sub = diag + (read[i - 1] != ref[lo + j - 1] ? 1 : 0);
+            if (sub < best)
+                best = sub;
+            diag = up;
+            row[j] = best;
+        }
+    }
+    int32_t m = row[0];
+    for (uint64_t j = 1; j <= n; j++)
+        if (row[j] < m)
+            m = row[j];
+    return m;
+}

@@ -133,6 +133,9 @@ _SIGS = {
     "grim_survivors_workspace_size": (ctypes.c_int, [_u64, _P(_u64)]),
     "grim_compact_survivors": (ctypes.c_int, [_P(grim_batch_t), _vp, _u64, _vp, _vp, _vp, _vp, _vp,
                                               _u64, _vp]),
+    "grim_index_attach_reference": (ctypes.c_int, [_vp, _vp, _u64, _vp]),
+    "grim_verify_survivors": (ctypes.c_int, [_vp, _P(grim_batch_t), _vp, _vp, _u64, _vp, _vp,
+                                             _vp]),
     "grim_graph_create": (ctypes.c_int, [_vp, _P(grim_batch_t), _vp, _vp, _vp, _u64,
                                          _P(grim_tuning_t), _P(_vp)]),
     "grim_graph_launch": (ctypes.c_int, [_vp, _vp]),
@@ -263,6 +266,13 @@ class Index:
         _check(_lib.grim_index_copy_to_host(self._h, out.ctypes.data_as(_vp), out.nbytes),
                "grim_index_copy_to_host")
         return out
+
+    def attach_reference(self, ref, stream=None):
+        """Keep the packed reference on the device (for grim_verify_survivors)."""
+        words = grim_pack_bases(ref)
+        _check(_lib.grim_index_attach_reference(self._h, words.ctypes.data_as(_vp),
+                                                int(np.asarray(ref).size), _stream(stream)),
+               "grim_index_attach_reference")
 
     def save(self, path):
         _check(_lib.grim_index_save(self._h, str(path).encode()), "grim_index_save")
@@ -419,6 +429,19 @@ def grim_compact_survivors(batch, pass_bits, capacity=None, stream=None):
     total = int(n.item())
     k = min(total, cap)
     return sp[:k], sr[:k], sb[:k], total
+
+
+def grim_verify_survivors(index, batch, surv_read, surv_bin, n=None, stream=None):
+    """Alignment check of survivors: (dist int32[n], ok_bits int32[ceil(n/32)])."""
+    torch = _torch()
+    dev = surv_read.device
+    n = int(surv_read.numel()) if n is None else int(n)
+    dist = torch.empty(max(1, n), dtype=torch.int32, device=dev)
+    ok = torch.empty(max(1, (n + 31) // 32), dtype=torch.int32, device=dev)
+    _check(_lib.grim_verify_survivors(index.handle, ctypes.byref(batch.c), _ptr(surv_read),
+                                      _ptr(surv_bin), n, _ptr(dist), _ptr(ok), _stream(stream)),
+           "grim_verify_survivors")
+    return dist[:n], ok[:(n + 31) // 32]
 
 
 class Graph:

@@ -327,6 +327,8 @@ extern "C" int grim_build_bins(const uint32_t *ref_2bit, uint64_t ref_len, const
     grim_index *idx = new (std::nothrow) grim_index();
     if (!idx)
         return GRIM_E_NOMEM;
+    idx->d_ref = nullptr;
+    idx->ref_words = 0;
     idx->q = p->q;
     idx->device = dev;
     idx->B = p->bin_stride;
@@ -474,6 +476,8 @@ extern "C" int grim_index_load(const char *path, grim_index_t **out, void *strea
     grim_index *idx = new (std::nothrow) grim_index();
     if (!idx)
         return GRIM_E_NOMEM;
+    idx->d_ref = nullptr;
+    idx->ref_words = 0;
     idx->q = h.q;
     idx->device = dev;
     idx->B = h.B;
@@ -503,6 +507,8 @@ extern "C" void grim_index_free(grim_index_t *idx)
 {
     if (!idx)
         return;
+    if (idx->d_ref)
+        (void)hipFree(idx->d_ref);
     (void)hipFree(idx->d_vec);
     delete idx;
 }
@@ -713,6 +719,77 @@ extern "C" int grim_compact_survivors(const grim_batch_t *b, const uint32_t *pas
     HIP_TRY(launch_compact(reinterpret_cast<hipStream_t>(stream), pass_bits, b->n_pairs,
                            b->cand_off, b->n_reads, b->cand_bin, capacity, surv_pair, surv_read,
                            surv_bin, n_survivors, reinterpret_cast<uint64_t *>(workspace)));
+    return GRIM_OK;
+}
+
+extern "C" int grim_index_attach_reference(grim_index_t *idx, const uint32_t *ref_2bit,
+                                           uint64_t ref_len, void *stream)
+{
+    if (!idx || !ref_2bit || ref_len != idx->G)
+        return GRIM_E_INVALID;
+    const uint64_t nw = grim_packed_words(ref_len);
+    uint32_t *d = nullptr;
+    if (hipMalloc(&d, nw * 4) != hipSuccess)
+        return GRIM_E_NOMEM;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e = hipMemcpyAsync(d, ref_2bit, nw * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        (void)hipFree(d);
+        return hip_fail(e, "grim_index_attach_reference");
+    }
+    if (idx->d_ref)
+        (void)hipFree(idx->d_ref);
+    idx->d_ref = d;
+    idx->ref_words = nw;
+    return GRIM_OK;
+}
+
+extern "C" int grim_verify_survivors(const grim_index_t *idx, const grim_batch_t *b,
+                                     const uint32_t *surv_read, const uint32_t *surv_bin,
+                                     uint64_t n_survivors, int32_t *dist, uint32_t *ok_bits,
+                                     void *stream)
+{
+    int rc = check_batch(idx, b);
+    if (rc)
+        return rc;
+    if (!idx->d_ref)
+        return GRIM_E_INVALID;
+    if (n_survivors && (!surv_read || !surv_bin || !dist || !ok_bits))
+        return GRIM_E_INVALID;
+    const int W = b->max_len <= 64 ? 1 : b->max_len <= 128 ? 2 : b->max_len <= 256 ? 4
+                : b->max_len <= 512 ? 8 : 0;
+    if (!W)
+        return GRIM_E_UNSUPPORTED;
+    if (n_survivors == 0)
+        return GRIM_OK;
+    VerifyArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.ref = idx->d_ref;
+    a.ref_words = idx->ref_words;
+    a.G = idx->G;
+    a.B = idx->B;
+    a.O = idx->O;
+    a.n_bins = idx->n_bins;
+    a.rw = b->reads_2bit;
+    a.nw = b->n_read_words;
+    a.read_off = b->read_off;
+    a.read_len = b->read_len;
+    a.read_e = b->read_e;
+    a.e_den = b->e_den;
+    a.n_reads = b->n_reads;
+    a.surv_read = surv_read;
+    a.surv_bin = surv_bin;
+    a.n_surv = n_survivors;
+    a.dist = dist;
+    a.ok_bits = ok_bits;
+    const uint64_t waves = (n_survivors + 63) / 64;
+    uint64_t grid = (waves + 3) / 4;
+    const uint64_t cap = (uint64_t)cu_count(idx->device) * 16;
+    if (grid > cap)
+        grid = cap;
+    HIP_TRY(launch_verify(reinterpret_cast<hipStream_t>(stream), W, (uint32_t)grid, a));
     return GRIM_OK;
 }
 

@@ -184,4 +184,122 @@ uint64_t compact_blocks(uint64_t n_pairs)
     return (n_words + kCompactWpb - 1) / kCompactWpb;
 }
 
+
+// ---------------------------------------------------- alignment check
+// Smallest edit distance between a surviving read and any substring of its
+// bin's span (free start and end in the reference), i.e. whether the
+// location really holds the read within E edits.  Computed with Myers'
+// bit-parallel approximate-matching recurrence (G. Myers, J. ACM 46(3), 1999),
+// in its block form: the read is split into W 64-row blocks; for every
+// reference base each block updates its vertical delta vectors (Pv, Mv) and
+// passes the horizontal delta of its last row to the next block.  One thread
+// per survivor; the read's match masks live in registers.
+__device__ __forceinline__ uint32_t base_at(const uint32_t *__restrict__ w, uint64_t nw, uint64_t p)
+{
+    const uint64_t wi = p >> 4;
+    const uint32_t x = wi < nw ? w[wi] : 0u;
+    return (x >> (30 - 2 * (uint32_t)(p & 15))) & 3u;
+}
+
+template <int W>
+__global__ __launch_bounds__(256) void verify_kernel(VerifyArgs a)
+{
+    const int lane = threadIdx.x & 63;
+    const uint64_t stride = (uint64_t)gridDim.x * (blockDim.x >> 6) * 64;
+    for (uint64_t base = ((uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 64;
+         base < a.n_surv; base += stride) {
+        const uint64_t i = base + lane;
+        int32_t d = -1;
+        bool ok = false;
+        if (i < a.n_surv) {
+            const uint32_t r = a.surv_read[i], b = a.surv_bin[i];
+            const uint64_t nb = a.nw * 16;
+            const uint32_t L = r < a.n_reads ? a.read_len[r] : 0u;
+            const uint64_t off = r < a.n_reads ? a.read_off[r] : 0u;
+            if (r < a.n_reads && b < a.n_bins && L <= 64u * W && off <= nb && L <= nb - off) {
+                const uint32_t E =
+                    (uint32_t)(((uint64_t)a.read_e[r] * L + a.e_den - 1) / a.e_den);
+                uint64_t pa[W], pc[W], pg[W], pt[W], Pv[W], Mv[W];
+#pragma unroll
+                for (int w = 0; w < W; ++w) {
+                    pa[w] = pc[w] = pg[w] = pt[w] = 0;
+                    Pv[w] = ~0ull;
+                    Mv[w] = 0;
+                    for (uint32_t k = 0; k < 64; ++k) {
+                        const uint32_t p = 64u * w + k;
+                        if (p >= L)
+                            break;
+                        const uint32_t cb = base_at(a.rw, a.nw, off + p);
+                        const uint64_t bit = 1ull << k;
+                        pa[w] |= cb == 0 ? bit : 0ull;
+                        pc[w] |= cb == 1 ? bit : 0ull;
+                        pg[w] |= cb == 2 ? bit : 0ull;
+                        pt[w] |= cb == 3 ? bit : 0ull;
+                    }
+                }
+                const int wu = (int)((L + 63) >> 6);
+                const uint64_t hb = 1ull << ((L - 1) & 63);
+                const uint64_t lo = (uint64_t)b * a.B;
+                uint64_t hi = lo + a.B + a.O;
+                if (hi > a.G)
+                    hi = a.G;
+                int32_t score = (int32_t)L, best = (int32_t)L;
+                for (uint64_t j = lo; j < hi; ++j) {
+                    const uint32_t cb = base_at(a.ref, a.ref_words, j);
+                    int h = 0;
+#pragma unroll
+                    for (int w = 0; w < W; ++w) {
+                        if (w < wu) {
+                            uint64_t eq = cb == 0 ? pa[w] : cb == 1 ? pc[w] : cb == 2 ? pg[w] : pt[w];
+                            const uint64_t xv = eq | Mv[w];
+                            if (h < 0)
+                                eq |= 1ull;
+                            const uint64_t xh = (((eq & Pv[w]) + Pv[w]) ^ Pv[w]) | eq;
+                            uint64_t ph = Mv[w] | ~(xh | Pv[w]);
+                            uint64_t mh = Pv[w] & xh;
+                            const uint64_t top = (w == wu - 1) ? hb : (1ull << 63);
+                            const int hout = (ph & top) ? 1 : ((mh & top) ? -1 : 0);
+                            ph <<= 1;
+                            mh <<= 1;
+                            if (h < 0)
+                                mh |= 1ull;
+                            else if (h > 0)
+                                ph |= 1ull;
+                            Pv[w] = mh | ~(xv | ph);
+                            Mv[w] = ph & xv;
+                            h = hout;
+                        }
+                    }
+                    score += h;
+                    best = min(best, score);
+                }
+                d = min<int32_t>(best, (int32_t)E + 1);
+                ok = best <= (int32_t)E;
+            }
+            a.dist[i] = d;
+        }
+        const uint64_t m = __ballot(ok);
+        const uint64_t n_words = (a.n_surv + 31) / 32;
+        if (lane == 0)
+            a.ok_bits[base >> 5] = (uint32_t)m;
+        if (lane == 32 && (base >> 5) + 1 < n_words)
+            a.ok_bits[(base >> 5) + 1] = (uint32_t)(m >> 32);
+    }
+}
+
+hipError_t launch_verify(hipStream_t s, int W, uint32_t grid, const VerifyArgs &a)
+{
+    VerifyArgs copy = a;
+    void *args[] = {&copy};
+    const void *k = nullptr;
+    switch (W) {
+    case 1: k = reinterpret_cast<const void *>(&verify_kernel<1>); break;
+    case 2: k = reinterpret_cast<const void *>(&verify_kernel<2>); break;
+    case 4: k = reinterpret_cast<const void *>(&verify_kernel<4>); break;
+    case 8: k = reinterpret_cast<const void *>(&verify_kernel<8>); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipLaunchKernel(k, dim3(grid), dim3(256), args, 0, s);
+}
+
 }  // namespace grim

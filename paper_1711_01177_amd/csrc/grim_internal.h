@@ -38,6 +38,25 @@ struct FilterArgs {
     int npl;                    // multiplicity planes reserved per read
 };
 
+// Arguments of the alignment-check kernel.
+struct VerifyArgs {
+    const uint32_t *ref;        // packed reference
+    uint64_t ref_words;
+    uint64_t G, B, O, n_bins;
+    const uint32_t *rw;
+    uint64_t nw;
+    const uint64_t *read_off;
+    const uint32_t *read_len;
+    const uint32_t *read_e;
+    uint32_t e_den;
+    uint64_t n_reads;
+    const uint32_t *surv_read;
+    const uint32_t *surv_bin;
+    uint64_t n_surv;
+    int32_t *dist;
+    uint32_t *ok_bits;
+};
+
 struct BatchedVariant {
     int q, g, u;
     const void *kernel;
@@ -57,6 +76,7 @@ hipError_t launch_compact(hipStream_t s, const uint32_t *bits, uint64_t n_pairs,
                           uint64_t cap, uint64_t *surv_pair, uint32_t *surv_read,
                           uint32_t *surv_bin, uint64_t *n_out, uint64_t *block_sums);
 uint64_t compact_blocks(uint64_t n_pairs);
+hipError_t launch_verify(hipStream_t s, int W, uint32_t grid, const VerifyArgs &a);
 hipError_t launch_filter(const void *kernel, dim3 grid, dim3 block, size_t lds_bytes,
                          hipStream_t s, const FilterArgs &a);
 
@@ -68,4 +88,6 @@ struct grim_index {
     int device;
     uint64_t B, O, G, n_bins, vector_bytes, bytes;
     void *d_vec;
+    uint32_t *d_ref;        // packed reference kept for alignment checks (or null)
+    uint64_t ref_words;
 };

@@ -381,6 +381,49 @@ def check_survivor_list(orc):
     assert sp.size == 0
 
 
+def levenshtein(a, b):
+    """Plain Levenshtein distance (full table)."""
+    prev = list(range(len(b) + 1))
+    for i in range(1, len(a) + 1):
+        cur = [i] + [0] * len(b)
+        for j in range(1, len(b) + 1):
+            cur[j] = min(prev[j] + 1, cur[j - 1] + 1, prev[j - 1] + (a[i - 1] != b[j - 1]))
+        prev = cur
+    return prev[-1]
+
+
+def check_edit_distance_in_bin(orc):
+    """Verification distance: the minimum, over every substring of the bin's
+    span, of the Levenshtein distance to the read -- by brute force over all
+    substrings on small cases, plus hand values."""
+    assert orc.edit_distance_in_bin(enc("AAACGTAAA"), 100, 0, 0, enc("ACGT")) == 0
+    assert orc.edit_distance_in_bin(enc("AAAGTAAA"), 100, 0, 0, enc("ACGT")) == 1
+    assert orc.edit_distance_in_bin(enc("TTTT"), 100, 0, 0, enc("ACGT")) == 3
+    assert orc.edit_distance_in_bin(enc("TTTT"), 100, 0, 0, enc("")) == 0
+    assert orc.edit_distance_in_bin(enc("ACCGT"), 100, 0, 0, enc("ACGT")) == 1
+    rng = random.Random(19)
+    for _ in range(120):
+        G = rng.randrange(1, 40)
+        ref_s = "".join(rng.choice("ACGT") for _ in range(G))
+        B = rng.randrange(3, 20)
+        O = rng.randrange(0, 10)
+        b = rng.randrange(0, -(-G // B))
+        lo, hi = b * B, min(G, (b + 1) * B + O)
+        seg = ref_s[lo:hi]
+        if rng.random() < 0.5 and len(seg) > 2:
+            a = rng.randrange(0, len(seg) - 1)
+            r = list(seg[a:a + rng.randrange(1, len(seg) - a + 1)])
+            for _ in range(rng.randrange(0, 3)):
+                r[rng.randrange(len(r))] = rng.choice("ACGT")
+            read = "".join(r)
+        else:
+            read = "".join(rng.choice("ACGT") for _ in range(rng.randrange(0, 12)))
+        want = min(levenshtein(read, seg[x:y]) for x in range(len(seg) + 1)
+                   for y in range(x, len(seg) + 1))
+        got = orc.edit_distance_in_bin(enc(ref_s), B, O, b, enc(read))
+        assert got == want, (ref_s, B, O, b, read, got, want)
+
+
 ALL_CHECKS = [
     check_golden_hand_vectors,
     check_all_a_example,
@@ -396,4 +439,5 @@ ALL_CHECKS = [
     check_edges,
     check_bitmask_packing,
     check_survivor_list,
+    check_edit_distance_in_bin,
 ]

@@ -4,7 +4,7 @@ import pytest
 
 import grim_synth as gs
 import oracle
-from tests.gpu_helpers import gpu_index, gpu_run, lib, oracle_run
+from tests.gpu_helpers import custom_workload, gpu_index, gpu_run, lib, oracle_run
 
 pytestmark = pytest.mark.gpu
 
@@ -73,3 +73,90 @@ def test_survivors_edges():
               cand_off=np.zeros(1, np.uint64), cand_bin=np.zeros(0, np.uint32))
     sp, sr, sb, total = _compact(g, w0, np.zeros(1, np.uint32))
     assert total == 0
+
+
+def _verify_gpu(g, idx, w, surv_read, surv_bin, max_len=None):
+    import torch
+    batch = g.Batch.from_workload(w, max_len=max_len)
+    sr = torch.from_numpy(np.ascontiguousarray(surv_read, dtype=np.uint32).view(np.int32)).cuda()
+    sb = torch.from_numpy(np.ascontiguousarray(surv_bin, dtype=np.uint32).view(np.int32)).cuda()
+    dist, ok = g.grim_verify_survivors(idx, batch, sr, sb, len(surv_read))
+    torch.cuda.synchronize()
+    return dist.cpu().numpy(), ok.cpu().numpy().view(np.uint32)
+
+
+@pytest.mark.parametrize("name,scale", [("tiny", 1.0), ("batched", 0.002)])
+def test_verify_survivors_match_oracle(name, scale):
+    import torch
+    g = lib()
+    w = gs.make_workload(name, scale=scale)
+    idx = gpu_index(w)
+    idx.attach_reference(w["ref"])
+    batch = g.Batch.from_workload(w)
+    c, bits = g.alloc_outputs(batch.n_pairs)
+    ws = g.alloc_workspace(idx, batch.n_pairs)
+    g.grim_filter_batch(idx, batch, c, bits, ws)
+    sp, sr, sb, total = g.grim_compact_survivors(batch, bits)
+    dist, ok = g.grim_verify_survivors(idx, batch, sr, sb, total)
+    torch.cuda.synchronize()
+    srn = sr.cpu().numpy().view(np.uint32)
+    sbn = sb.cpu().numpy().view(np.uint32)
+    want = oracle.verify(w["ref"], w["B"], w["O"], w["codes"], w["read_off"], w["read_len"],
+                         w["read_e"], w["e_den"], srn, sbn)
+    got = dist.cpu().numpy()
+    assert np.array_equal(got, want), np.nonzero(got != want)[0][:5]
+    E = (w["read_e"].astype(np.int64) * w["read_len"] + w["e_den"] - 1) // w["e_den"]
+    okb = ok.cpu().numpy().view(np.uint32)
+    okn = (okb[np.arange(total) >> 5] >> (np.arange(total) & 31)) & 1
+    assert np.array_equal(okn.astype(bool), want <= E[srn])
+    # every read's true location survives and verifies (planted edits <= E)
+    spn = sp.cpu().numpy()
+    true_set = set(w["true_pair"].tolist())
+    verified_true = sum(1 for k, o in zip(spn.tolist(), okn.tolist()) if k in true_set and o)
+    assert verified_true == len(true_set)
+
+
+def test_verify_edges():
+    g = lib()
+    ref = gs.reference(8, 60_000, 0.3, 5, 300, 0.85, 0.98)
+    q, B, O = 5, 200, 600
+    nb = (ref.size + B - 1) // B
+    rng = np.random.default_rng(4)
+    reads, cands = [], []
+    for L in (0, 1, 5, 63, 64, 65, 128, 129, 256, 300, 512):
+        st = int(rng.integers(0, ref.size - L - 1))
+        r = ref[st:st + L].copy()
+        if L > 10:
+            for _ in range(3):
+                r[int(rng.integers(0, L))] = int(rng.integers(0, 4))
+        reads.append(r)
+        cands.append([st // B, int(rng.integers(0, nb)), nb - 1])
+    e = [1000] * len(reads)
+    w = custom_workload(ref, q, B, O, reads, cands, e)
+    idx = g.grim_build_bins(ref, q, B, O)
+    idx.attach_reference(ref)
+    off = w["cand_off"]
+    surv_read = np.repeat(np.arange(len(reads), dtype=np.uint32), np.diff(off.astype(np.int64)))
+    surv_bin = w["cand_bin"].copy()
+    surv_bin[4] = nb + 3  # out of range -> -1
+    for max_len in (512,):
+        dist, okb = _verify_gpu(g, idx, w, surv_read, surv_bin, max_len=max_len)
+        want = oracle.verify(ref, B, O, w["codes"], w["read_off"], w["read_len"], w["read_e"],
+                             w["e_den"], surv_read, np.where(surv_bin < nb, surv_bin, 0))
+        want[4] = -1
+        assert np.array_equal(dist, want), (dist, want)
+    # short batches use the narrower kernels (1 and 2 blocks of 64 rows)
+    for Lmax in (64, 128):
+        sel = [i for i, r in enumerate(reads) if len(r) <= Lmax]
+        w2 = custom_workload(ref, q, B, O, [reads[i] for i in sel], [cands[i] for i in sel],
+                             [e[i] for i in sel])
+        off2 = w2["cand_off"]
+        sr2 = np.repeat(np.arange(len(sel), dtype=np.uint32), np.diff(off2.astype(np.int64)))
+        dist, _ = _verify_gpu(g, idx, w2, sr2, w2["cand_bin"], max_len=Lmax)
+        want = oracle.verify(ref, B, O, w2["codes"], w2["read_off"], w2["read_len"],
+                             w2["read_e"], w2["e_den"], sr2, w2["cand_bin"])
+        assert np.array_equal(dist, want)
+    # reads longer than 512 are not supported by the alignment check
+    with pytest.raises(g.GrimError) as ex:
+        _verify_gpu(g, idx, w, surv_read, surv_bin, max_len=600)
+    assert ex.value.code == g.GRIM_E_UNSUPPORTED

@@ -42,6 +42,13 @@ MUTANTS = {
                           "words[k >> 5] |= 1u << (31 - (k & 31));"),
     "survivor_read_off_by_one": ("surv_read[n] = (uint32_t)r;", "surv_read[n] = (uint32_t)(r + 1);"),
     "survivor_bit_inverted": ("if (!((words[k >> 5] >> (k & 31)) & 1u))", "if (((words[k >> 5] >> (k & 31)) & 1u))"),
+    "verify_span_without_overlap": ("uint64_t hi = B * (b + 1) + O;", "uint64_t hi = B * (b + 1);"),
+    "verify_free_start_dropped": ("row[j] = 0;                                   /* D[0][j] = 0 */",
+                                  "row[j] = (int32_t)j;"),
+    "verify_substitution_free": ("int32_t sub = diag + (read[i - 1] != ref[lo + j - 1] ? 1 : 0);",
+                                 "int32_t sub = diag;"),
+    "verify_last_column_only": ("    int32_t m = row[0];\n    for (uint64_t j = 1; j <= n; j++)\n        if (row[j] < m)\n            m = row[j];",
+                                "    int32_t m = row[n];"),
     "bin_wrong_vector": ("const uint8_t *vec = index + b * nbytes;     /* step 2 */",
                          "const uint8_t *vec = index + (b ^ 1) % n_bins * nbytes;"),
 }
