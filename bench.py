@@ -93,49 +93,68 @@ def cpu_baseline(w, target_pairs, n_threads):
                 pairs_per_s=n_pairs / dt), (c, p), idx
 
 
-def serving_leg(g, idx, w, seconds, load_rps, rng, max_reads=65536):
-    """Poisson arrivals of requests with log-uniform sizes (1..max_reads reads)
-    cut from the workload; returns the server's statistics."""
+def serving_leg(g, idx, w, rng, loads=(0.25, 0.5, 0.75), seconds=2.5, max_reads=65536):
+    """Served latency.  Requests of log-uniform size (1..max_reads reads) are cut
+    from the workload.  First the server's capacity is measured closed-loop
+    (a burst of requests submitted at once); then, for each offered load rho,
+    requests arrive as a Poisson process at rho x capacity for `seconds`, and the
+    server's p50/p99 latency (submit -> results in host memory) is recorded."""
     n_reads = w["read_len"].size
     reqs = []
-    total = 0
-    n_req = max(8, int(seconds * load_rps))
-    for _ in range(n_req):
+    for _ in range(120):
         size = int(min(n_reads, max(1, round(math.exp(rng.uniform(0, math.log(max_reads)))))))
         r0 = int(rng.integers(0, n_reads - size + 1))
         r1 = r0 + size
         o0 = int(w["read_off"][r0])
         o1 = int(w["read_off"][r1 - 1]) + int(w["read_len"][r1 - 1])
         c0, c1 = int(w["cand_off"][r0]), int(w["cand_off"][r1])
-        hb = g.HostBatch(w["codes"][o0:o1], w["read_off"][r0:r1] - o0, w["read_len"][r0:r1],
-                         w["read_e"][r0:r1], w["e_den"], w["cand_off"][r0:r1 + 1] - c0,
-                         w["cand_bin"][c0:c1], max_len=250)
-        reqs.append(hb)
-        total += hb.n_pairs
-    srv = g.Server(idx, hbm_budget_bytes=16 << 30, max_inflight=64, n_streams=2,
+        reqs.append(g.HostBatch(w["codes"][o0:o1], w["read_off"][r0:r1] - o0, w["read_len"][r0:r1],
+                                w["read_e"][r0:r1], w["e_den"], w["cand_off"][r0:r1 + 1] - c0,
+                                w["cand_bin"][c0:c1], max_len=250))
+    mean_pairs = float(np.mean([hb.n_pairs for hb in reqs]))
+    srv = g.Server(idx, hbm_budget_bytes=4 << 30, max_inflight=64, n_streams=3,
                    max_tick_pairs=64 << 20, max_len=256)
-    gaps = rng.exponential(1.0 / load_rps, size=len(reqs))
-    tickets = []
-    t_start = time.perf_counter()
-    t_next = t_start
-    for hb, gap in zip(reqs, gaps):
-        t_next += gap
-        d = t_next - time.perf_counter()
-        if d > 0:
-            time.sleep(d)
-        tickets.append(srv.submit(hb))
-    for t in tickets:
-        rc, _, _, _ = srv.wait(t)
-        if rc not in (0,):
-            raise RuntimeError(f"serving request failed: {rc}")
-    wall = time.perf_counter() - t_start
-    st = srv.stats()
+
+    def drain(tickets):
+        for t in tickets:
+            rc, _, _, _ = srv.wait(t)
+            if rc != 0:
+                raise RuntimeError(f"serving request failed: {rc}")
+
+    # closed-loop capacity
+    t0 = time.perf_counter()
+    drain([srv.submit(hb) for hb in reqs[:60]])
+    cap_wall = time.perf_counter() - t0
+    cap_pairs = sum(hb.n_pairs for hb in reqs[:60])
+    capacity = cap_pairs / cap_wall
+    srv.stats(reset=True)
+    out = dict(requests_per_point=None, mean_pairs_per_request=mean_pairs,
+               capacity_pairs_per_s=capacity, points=[])
+    for rho in loads:
+        rate = rho * capacity / mean_pairs          # requests per second
+        n = int(max(20, min(400, rate * seconds)))
+        gaps = rng.exponential(1.0 / rate, size=n)
+        tickets = []
+        waiter_tickets = []
+        t_start = time.perf_counter()
+        t_next = t_start
+        for i in range(n):
+            t_next += gaps[i]
+            d = t_next - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            tickets.append(srv.submit(reqs[i % len(reqs)]))
+        drain(tickets)
+        wall = time.perf_counter() - t_start
+        st = srv.stats(reset=True)
+        out["points"].append(dict(offered_load=rho, offered_rps=rate, requests=n, wall_s=wall,
+                                  p50_ms=st["p50_ms"], p99_ms=st["p99_ms"], mean_ms=st["mean_ms"],
+                                  max_ms=st["max_ms"], pairs_per_s=st["pairs_done"] / wall,
+                                  mean_requests_per_tick=st["mean_requests_per_tick"]))
     srv.destroy()
-    return dict(requests=len(reqs), offered_rps=load_rps, pairs=total, wall_s=wall,
-                p50_ms=st["p50_ms"], p99_ms=st["p99_ms"], mean_ms=st["mean_ms"],
-                max_ms=st["max_ms"], pairs_per_s_busy=st["pairs_per_s"],
-                pairs_per_s_wall=total / wall, ticks=st["ticks"],
-                mean_requests_per_tick=st["mean_requests_per_tick"])
+    mid = out["points"][len(out["points"]) // 2]
+    out["p50_ms"], out["p99_ms"] = mid["p50_ms"], mid["p99_ms"]
+    return out
 
 
 def main():
@@ -326,8 +345,12 @@ def main():
     if not args.no_serve:
         try:
             t0 = time.time()
-            serving = serving_leg(g, idx, w, seconds=4.0, load_rps=40.0, rng=rng)
-            log(f"[bench] serving: p50 {serving['p50_ms']:.2f} ms p99 {serving['p99_ms']:.2f} ms "
+            serving = serving_leg(g, idx, w, rng)
+            for pt in serving["points"]:
+                log(f"[bench] serving at {pt['offered_load']:.2f} x capacity "
+                    f"({pt['offered_rps']:.0f} req/s): p50 {pt['p50_ms']:.2f} ms "
+                    f"p99 {pt['p99_ms']:.2f} ms, {pt['pairs_per_s']:.3e} pairs/s")
+            log(f"[bench] serving capacity {serving['capacity_pairs_per_s']:.3e} pairs/s "
                 f"({time.time() - t0:.1f}s)")
         except Exception as ex:  # report, keep the throughput line
             serving = dict(error=str(ex))

@@ -1,13 +1,20 @@
 // Continuous-batching server for GRIM-Filter requests.
 //
-// Requests are host batches (reads + candidate locations).  A scheduler thread
-// repeatedly (1) retires finished ticks, copying each request's slice of the
-// fused outputs back into its own result buffers, and (2) when a stream slot is
-// free, admits queued requests in arrival order while their device bytes fit in
-// what is left of the HBM budget, fuses them into one batch, and queues
-// H2D copy + batched filter launch + D2H copy on that slot's stream.  Ticks on
-// different streams overlap on the device, and requests that arrive while
-// ticks run join the next tick as soon as memory and a slot free up.
+// Requests are host batches (reads + candidate locations).  At submit the
+// request's arrays are copied once, into a block of a pinned host arena
+// allocated when the server is created (pageable memory only when the arena is
+// full), with room for its results.  A scheduler thread repeatedly
+//   (1) retires finished ticks: realigns each request's slice of the fused pass
+//       bits, and marks the requests done;
+//   (2) while a stream slot is free, admits queued requests in arrival order
+//       while their device bytes fit in what is left of the HBM budget, fuses
+//       them into one batch and queues on that slot's stream: H2D copies (large
+//       array slices straight from the request's pinned block, runs of small
+//       slices through the slot's staging buffer, re-based offset arrays always
+//       staged), one batched filter launch, and D2H copies (large count slices
+//       straight into the request's result area).
+// Ticks on different streams overlap on the device, and requests that arrive
+// while ticks run join the next tick as soon as memory and a slot free up.
 //
 // Fusing only concatenates and re-bases offsets, and every pair is computed by
 // the same kernel from the same read and bin, so each request's counts and
@@ -16,9 +23,10 @@
 
 #include <algorithm>
 #include <atomic>
-#include <cmath>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -40,66 +48,36 @@ double ms_between(Clock::time_point a, Clock::time_point b)
     return std::chrono::duration<double, std::milli>(b - a).count();
 }
 
-enum class State { Queued, Running, Done };
+// Slices at least this large move by DMA straight from / to the request's
+// block; smaller ones are packed through the slot's staging buffer.
+constexpr uint64_t kDirectBytes = 256 << 10;
 
-struct Request {
-    uint64_t ticket = 0;
-    std::vector<uint32_t> words;
-    std::vector<uint64_t> read_off, cand_off;
-    std::vector<uint32_t> read_len, read_e, cand_bin;
-    uint32_t e_den = 0;
-    uint64_t n_reads = 0, n_pairs = 0;
-    std::vector<int32_t> counts;
-    std::vector<uint32_t> bits;
-    State state = State::Queued;
-    bool cancelled = false;
-    int status = GRIM_OK;
-    uint32_t flags = 0;
-    uint64_t tick = 0;
-    Clock::time_point t_submit, t_admit, t_done;
-};
-
-// Byte layout of one fused tick; the same offsets are used in the pinned
-// staging buffer and in the device chunk.
-struct Layout {
-    uint64_t words, read_off, read_len, read_e, cand_off, cand_bin;  // inputs
-    uint64_t in_bytes;
-    uint64_t counts, bits, out_bytes;  // outputs, relative to `out_base`
-    uint64_t out_base;
-    uint64_t ws, ws_bytes;
-    uint64_t total;
-};
-
-Layout plan(uint64_t n_words, uint64_t n_reads, uint64_t n_pairs, uint64_t ws_bytes)
+// memcpy split over a few threads for large copies (host staging is the
+// bottleneck of served latency for big requests).
+void par_memcpy(void *dst, const void *src, uint64_t n)
 {
-    Layout L;
-    uint64_t o = 0;
-    L.words = o;
-    o = align256(o + n_words * 4);
-    L.read_off = o;
-    o = align256(o + n_reads * 8);
-    L.read_len = o;
-    o = align256(o + n_reads * 4);
-    L.read_e = o;
-    o = align256(o + n_reads * 4);
-    L.cand_off = o;
-    o = align256(o + (n_reads + 1) * 8);
-    L.cand_bin = o;
-    o = align256(o + n_pairs * 4);
-    L.in_bytes = o;
-    L.out_base = o;
-    L.counts = 0;
-    L.bits = align256(n_pairs * 4);
-    L.out_bytes = L.bits + align256(((n_pairs + 31) / 32) * 4 + 4);
-    o += L.out_bytes;
-    L.ws = o;
-    L.ws_bytes = align256(ws_bytes);
-    o += L.ws_bytes;
-    L.total = o;
-    return L;
+    constexpr uint64_t kChunk = 8ull << 20;
+    if (n < 2 * kChunk) {
+        if (n)
+            std::memcpy(dst, src, n);
+        return;
+    }
+    const int nt = (int)std::min<uint64_t>(8, n / kChunk);
+    const uint64_t step = (n + nt - 1) / nt;
+    std::vector<std::thread> th;
+    for (int t = 1; t < nt; ++t) {
+        const uint64_t a = t * step, b = std::min(n, a + step);
+        if (a < b)
+            th.emplace_back([=] {
+                std::memcpy(static_cast<char *>(dst) + a, static_cast<const char *>(src) + a, b - a);
+            });
+    }
+    std::memcpy(dst, src, std::min(n, step));
+    for (auto &x : th)
+        x.join();
 }
 
-// First-fit allocator over the server's device pool (offsets, 256-byte units).
+// First-fit allocator over a byte range (offsets, 256-byte units).
 class Pool {
 public:
     explicit Pool(uint64_t size) { free_[0] = size; }
@@ -144,19 +122,114 @@ private:
     uint64_t used_ = 0;
 };
 
+enum class State { Queued, Running, Done };
+
+// Host-side layout of one request's block: inputs, then result area.
+struct ReqLayout {
+    uint64_t words, read_off, read_len, read_e, cand_off, cand_bin, counts, bits, total;
+};
+
+ReqLayout req_layout(uint64_t n_words, uint64_t n_reads, uint64_t n_pairs)
+{
+    ReqLayout L;
+    uint64_t o = 0;
+    L.words = o;
+    o = align256(o + n_words * 4);
+    L.read_off = o;
+    o = align256(o + n_reads * 8);
+    L.read_len = o;
+    o = align256(o + n_reads * 4);
+    L.read_e = o;
+    o = align256(o + n_reads * 4);
+    L.cand_off = o;
+    o = align256(o + (n_reads + 1) * 8);
+    L.cand_bin = o;
+    o = align256(o + n_pairs * 4);
+    L.counts = o;
+    o = align256(o + n_pairs * 4);
+    L.bits = o;
+    o = align256(o + ((n_pairs + 31) / 32) * 4 + 4);
+    L.total = o;
+    return L;
+}
+
+struct Request {
+    uint64_t ticket = 0;
+    uint8_t *host = nullptr;       // block with inputs and results
+    bool pinned = false;           // block lives in the server's pinned arena
+    uint64_t arena_off = 0;
+    ReqLayout lay{};
+    uint64_t n_words = 0, n_reads = 0, n_pairs = 0;
+    uint32_t e_den = 0;
+    State state = State::Queued;
+    bool cancelled = false;
+    int status = GRIM_OK;
+    uint32_t flags = 0;
+    uint64_t tick = 0;
+    Clock::time_point t_submit, t_admit, t_done;
+
+    uint32_t *words() const { return reinterpret_cast<uint32_t *>(host + lay.words); }
+    uint64_t *read_off() const { return reinterpret_cast<uint64_t *>(host + lay.read_off); }
+    uint32_t *read_len() const { return reinterpret_cast<uint32_t *>(host + lay.read_len); }
+    uint32_t *read_e() const { return reinterpret_cast<uint32_t *>(host + lay.read_e); }
+    uint64_t *cand_off() const { return reinterpret_cast<uint64_t *>(host + lay.cand_off); }
+    uint32_t *cand_bin() const { return reinterpret_cast<uint32_t *>(host + lay.cand_bin); }
+    int32_t *counts() const { return reinterpret_cast<int32_t *>(host + lay.counts); }
+    uint32_t *bits() const { return reinterpret_cast<uint32_t *>(host + lay.bits); }
+};
+
+// Byte layout of one fused tick on the device (and in the staging buffer).
+struct Layout {
+    uint64_t words, read_off, read_len, read_e, cand_off, cand_bin;  // inputs
+    uint64_t in_bytes;
+    uint64_t counts, bits, status, out_bytes;  // outputs, relative to `out_base`
+    uint64_t out_base;
+    uint64_t ws, ws_bytes;
+    uint64_t total;
+};
+
+Layout plan(uint64_t n_words, uint64_t n_reads, uint64_t n_pairs, uint64_t ws_bytes)
+{
+    Layout L;
+    uint64_t o = 0;
+    L.words = o;
+    o = align256(o + n_words * 4);
+    L.read_off = o;
+    o = align256(o + n_reads * 8);
+    L.read_len = o;
+    o = align256(o + n_reads * 4);
+    L.read_e = o;
+    o = align256(o + n_reads * 4);
+    L.cand_off = o;
+    o = align256(o + (n_reads + 1) * 8);
+    L.cand_bin = o;
+    o = align256(o + n_pairs * 4);
+    L.in_bytes = o;
+    L.out_base = o;
+    L.counts = 0;
+    L.bits = align256(n_pairs * 4);
+    L.status = L.bits + align256(((n_pairs + 31) / 32) * 4 + 4);
+    L.out_bytes = L.status + 256;
+    o += L.out_bytes;
+    L.ws = o;
+    L.ws_bytes = align256(ws_bytes);
+    o += L.ws_bytes;
+    L.total = o;
+    return L;
+}
+
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
-    uint8_t *pinned = nullptr;
-    uint64_t pinned_bytes = 0;
+    uint8_t *stage = nullptr;      // pinned staging buffer, mirrors the tick layout
+    uint64_t stage_bytes = 0;
     bool busy = false;
-    // the tick in flight
     std::vector<std::shared_ptr<Request>> reqs;
     std::vector<uint64_t> pair_base;
+    std::vector<char> counts_direct;  // per request: counts came back by direct DMA
     Layout lay;
     uint64_t dev_off = 0;
     uint64_t tick = 0;
-    Clock::time_point t_launch;
 };
 
 }  // namespace
@@ -167,6 +240,10 @@ struct grim_server {
     int device = 0;
     uint8_t *pool_base = nullptr;
     std::unique_ptr<Pool> pool;
+    uint8_t *arena = nullptr;          // pinned host arena for request blocks
+    uint64_t arena_bytes = 0;
+    std::unique_ptr<Pool> arena_pool;
+    std::mutex arena_mu;
     std::vector<Slot> slots;
 
     std::mutex mu;
@@ -189,6 +266,7 @@ struct grim_server {
     void run();
     bool launch_tick(std::unique_lock<std::mutex> &lk);
     void retire(Slot &s);
+    void free_block(Request &r);
 };
 
 namespace {
@@ -200,43 +278,53 @@ uint64_t ws_need(const grim_index_t *idx, uint64_t n_pairs)
     return b;
 }
 
-// Device bytes one request adds to a tick.
-uint64_t request_bytes(const Request &r)
-{
-    return align256(r.words.size() * 4) + align256(r.n_reads * 8) + 2 * align256(r.n_reads * 4) +
-           align256((r.n_reads + 1) * 8) + 2 * align256(r.n_pairs * 4) +
-           align256(((r.n_pairs + 31) / 32) * 4 + 4) + align256(4 * ((r.n_pairs + 511) / 512) + 64);
-}
-
 }  // namespace
+
+void grim_server::free_block(Request &r)
+{
+    if (!r.host)
+        return;
+    if (r.pinned) {
+        std::lock_guard<std::mutex> lk(arena_mu);
+        arena_pool->release(r.arena_off, r.lay.total);
+    } else {
+        std::free(r.host);
+    }
+    r.host = nullptr;
+}
 
 void grim_server::retire(Slot &s)
 {
     // called with mu held, after s.done completed
-    const uint8_t *out = s.pinned + s.lay.out_base;
+    const uint8_t *out = s.stage + s.lay.out_base;
     const int32_t *counts = reinterpret_cast<const int32_t *>(out + s.lay.counts);
     const uint32_t *bits = reinterpret_cast<const uint32_t *>(out + s.lay.bits);
+    const uint32_t status = *reinterpret_cast<const uint32_t *>(out + s.lay.status);
     const auto now = Clock::now();
     for (size_t j = 0; j < s.reqs.size(); ++j) {
         Request &r = *s.reqs[j];
         const uint64_t base = s.pair_base[j];
         if (!r.cancelled) {
-            r.counts.assign(counts + base, counts + base + r.n_pairs);
+            if (!s.counts_direct[j] && r.n_pairs)
+                std::memcpy(r.counts(), counts + base, r.n_pairs * 4);
             const uint64_t nw = (r.n_pairs + 31) / 32;
-            r.bits.assign(nw, 0u);
+            uint32_t *rb = r.bits();
             const uint64_t w0 = base >> 5;
             const uint32_t sh = (uint32_t)(base & 31);
             for (uint64_t w = 0; w < nw; ++w) {
                 uint32_t x = bits[w0 + w] >> sh;
                 if (sh && (w0 + w + 1) * 32 < base + r.n_pairs)
                     x |= bits[w0 + w + 1] << (32 - sh);
-                r.bits[w] = x;
+                rb[w] = x;
             }
             if (r.n_pairs & 31)
-                r.bits[nw - 1] &= (1u << (r.n_pairs & 31)) - 1u;
+                rb[nw - 1] &= (1u << (r.n_pairs & 31)) - 1u;
             bool bad = false;
-            for (uint64_t k = 0; k < r.n_pairs && !bad; ++k)
-                bad = r.counts[k] < 0;
+            if (status & GRIM_FLAG_BIN_RANGE) {  // only then look for -1 in this request
+                const int32_t *c = r.counts();
+                for (uint64_t k = 0; k < r.n_pairs && !bad; ++k)
+                    bad = c[k] < 0;
+            }
             r.flags = bad ? GRIM_FLAG_BIN_RANGE : 0u;
             r.status = bad ? GRIM_E_BIN_RANGE : GRIM_OK;
             if (bad)
@@ -255,11 +343,55 @@ void grim_server::retire(Slot &s)
     pool->release(s.dev_off, s.lay.total);
     s.reqs.clear();
     s.pair_base.clear();
+    s.counts_direct.clear();
     s.busy = false;
     if (--running_ticks == 0)
         busy_s += std::chrono::duration<double>(now - busy_since).count();
     cv_done.notify_all();
 }
+
+namespace {
+
+// Queues the H2D copies of one array section: every request's slice of `bytes`
+// goes to dev + sec_off + slice offset; large slices by DMA from the request's
+// block, consecutive small slices packed in the stage and sent as one run.
+struct SectionCopier {
+    uint8_t *dev, *stage;
+    hipStream_t s;
+    uint64_t run_lo = 0, run_hi = 0;
+    bool run = false;
+    hipError_t err = hipSuccess;
+
+    void flush()
+    {
+        if (run && run_hi > run_lo && err == hipSuccess)
+            err = hipMemcpyAsync(dev + run_lo, stage + run_lo, run_hi - run_lo,
+                                 hipMemcpyHostToDevice, s);
+        run = false;
+    }
+    void add(uint64_t off, const void *src, uint64_t bytes)
+    {
+        if (!bytes)
+            return;
+        if (bytes >= kDirectBytes) {
+            flush();
+            if (err == hipSuccess)
+                err = hipMemcpyAsync(dev + off, src, bytes, hipMemcpyHostToDevice, s);
+            return;
+        }
+        std::memcpy(stage + off, src, bytes);
+        if (run && off == run_hi) {
+            run_hi = off + bytes;
+        } else {
+            flush();
+            run = true;
+            run_lo = off;
+            run_hi = off + bytes;
+        }
+    }
+};
+
+}  // namespace
 
 // Form and launch one tick on a free slot.  Returns false if nothing could be
 // launched.  Called with mu held; drops it while staging.
@@ -271,44 +403,27 @@ bool grim_server::launch_tick(std::unique_lock<std::mutex> &lk)
             slot = &s;
             break;
         }
-    if (!slot)
-        return false;
-    while (!queue.empty() && queue.front()->cancelled) {
-        auto r = queue.front();
-        queue.pop_front();
-        r->status = GRIM_E_CANCELLED;
-        r->state = State::Done;
-        r->t_done = Clock::now();
-        ++cancelled;
-        cv_done.notify_all();
-    }
-    if (queue.empty())
+    if (!slot || queue.empty())
         return false;
     // admission: FIFO prefix with the head's e_den, within slots, pairs, budget
     std::vector<std::shared_ptr<Request>> take;
-    uint64_t words = 0, reads = 0, pairs = 0, bytes = 0;
+    uint64_t words = 0, reads = 0, pairs = 0;
     const uint32_t e_den = queue.front()->e_den;
     const uint64_t free_bytes = cfg.hbm_budget_bytes - pool->used();
     for (auto it = queue.begin(); it != queue.end();) {
         Request &r = **it;
-        if (r.cancelled) {
-            ++it;
-            continue;
-        }
         if (r.e_den != e_den || inflight_reqs + take.size() >= cfg.max_inflight)
             break;
         if (!take.empty() && pairs + r.n_pairs > cfg.max_tick_pairs)
             break;
-        const uint64_t nb = bytes + request_bytes(r);
-        const uint64_t total = plan(words + r.words.size() + 1, reads + r.n_reads,
-                                    pairs + r.n_pairs, ws_need(idx, pairs + r.n_pairs)).total;
+        const uint64_t total = plan(words + r.n_words + 1, reads + r.n_reads, pairs + r.n_pairs,
+                                    ws_need(idx, pairs + r.n_pairs)).total;
         if (total > free_bytes)
             break;
         take.push_back(*it);
-        words += r.words.size();
+        words += r.n_words;
         reads += r.n_reads;
         pairs += r.n_pairs;
-        bytes = nb;
         it = queue.erase(it);
     }
     if (take.empty())
@@ -342,45 +457,62 @@ bool grim_server::launch_tick(std::unique_lock<std::mutex> &lk)
 
     lk.unlock();
     int rc = GRIM_OK;
-    // pinned staging buffer of this slot (grown rarely)
-    if (slot->pinned_bytes < lay.total) {
-        if (slot->pinned)
-            (void)hipHostFree(slot->pinned);
-        uint64_t nb = std::max<uint64_t>(lay.total, slot->pinned_bytes * 2);
-        if (hipHostMalloc(reinterpret_cast<void **>(&slot->pinned), nb, hipHostMallocDefault) !=
+    if (slot->stage_bytes < lay.total) {
+        if (slot->stage)
+            (void)hipHostFree(slot->stage);
+        const uint64_t nb = std::max<uint64_t>(lay.total, slot->stage_bytes * 2);
+        if (hipHostMalloc(reinterpret_cast<void **>(&slot->stage), nb, hipHostMallocDefault) !=
             hipSuccess) {
-            slot->pinned = nullptr;
-            slot->pinned_bytes = 0;
+            slot->stage = nullptr;
+            slot->stage_bytes = 0;
             rc = GRIM_E_NOMEM;
         } else {
-            slot->pinned_bytes = nb;
+            slot->stage_bytes = nb;
         }
     }
     slot->pair_base.clear();
+    slot->counts_direct.assign(take.size(), 0);
     if (rc == GRIM_OK) {
-        uint8_t *h = slot->pinned;
+        uint8_t *h = slot->stage;
+        uint8_t *d = pool_base + off;
+        hipStream_t st = slot->stream;
+        SectionCopier cw{d, h, st}, cl{d, h, st}, ce{d, h, st}, cb{d, h, st};
         uint64_t wbase = 0, rbase = 0, pbase = 0;
+        uint64_t *ro = reinterpret_cast<uint64_t *>(h + lay.read_off);
         uint64_t *coff = reinterpret_cast<uint64_t *>(h + lay.cand_off);
         for (auto &rp : take) {
             Request &r = *rp;
-            std::memcpy(h + lay.words + wbase * 4, r.words.data(), r.words.size() * 4);
-            uint64_t *ro = reinterpret_cast<uint64_t *>(h + lay.read_off) + rbase;
-            for (uint64_t i = 0; i < r.n_reads; ++i)
-                ro[i] = r.read_off[i] + wbase * 16;
-            std::memcpy(h + lay.read_len + rbase * 4, r.read_len.data(), r.n_reads * 4);
-            std::memcpy(h + lay.read_e + rbase * 4, r.read_e.data(), r.n_reads * 4);
-            for (uint64_t i = 0; i < r.n_reads; ++i)
-                coff[rbase + i] = r.cand_off[i] + pbase;
-            if (r.n_pairs)
-                std::memcpy(h + lay.cand_bin + pbase * 4, r.cand_bin.data(), r.n_pairs * 4);
+            cw.add(lay.words + wbase * 4, r.words(), r.n_words * 4);
+            const uint64_t *sro = r.read_off(), *sco = r.cand_off();
+            for (uint64_t i = 0; i < r.n_reads; ++i) {
+                ro[rbase + i] = sro[i] + wbase * 16;
+                coff[rbase + i] = sco[i] + pbase;
+            }
+            cl.add(lay.read_len + rbase * 4, r.read_len(), r.n_reads * 4);
+            ce.add(lay.read_e + rbase * 4, r.read_e(), r.n_reads * 4);
+            cb.add(lay.cand_bin + pbase * 4, r.cand_bin(), r.n_pairs * 4);
             slot->pair_base.push_back(pbase);
-            wbase += r.words.size();
+            wbase += r.n_words;
             rbase += r.n_reads;
             pbase += r.n_pairs;
         }
         coff[rbase] = pbase;
-        reinterpret_cast<uint32_t *>(h + lay.words)[wbase] = 0u;
-        uint8_t *d = pool_base + off;
+        const uint32_t zero = 0;
+        cw.add(lay.words + wbase * 4, &zero, 4);  // trailing word read by tokens at the end
+        cw.flush();
+        cl.flush();
+        ce.flush();
+        cb.flush();
+        hipError_t e = cw.err != hipSuccess ? cw.err : cl.err != hipSuccess ? cl.err
+                     : ce.err != hipSuccess ? ce.err : cb.err;
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(d + lay.read_off, h + lay.read_off, rbase * 8,
+                               hipMemcpyHostToDevice, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(d + lay.cand_off, h + lay.cand_off, (rbase + 1) * 8,
+                               hipMemcpyHostToDevice, st);
+        if (e != hipSuccess)
+            rc = GRIM_E_HIP;
         grim_batch_t b;
         b.reads_2bit = reinterpret_cast<const uint32_t *>(d + lay.words);
         b.n_read_words = wbase + 1;
@@ -393,24 +525,56 @@ bool grim_server::launch_tick(std::unique_lock<std::mutex> &lk)
         b.cand_bin = reinterpret_cast<const uint32_t *>(d + lay.cand_bin);
         b.n_reads = rbase;
         b.n_pairs = pbase;
-        int32_t *dcounts = reinterpret_cast<int32_t *>(d + lay.out_base + lay.counts);
-        uint32_t *dbits = reinterpret_cast<uint32_t *>(d + lay.out_base + lay.bits);
-        if (hipMemcpyAsync(d, h, lay.in_bytes, hipMemcpyHostToDevice, slot->stream) != hipSuccess)
-            rc = GRIM_E_HIP;
+        uint8_t *dout = d + lay.out_base;
+        uint8_t *hout = h + lay.out_base;
+        int32_t *dcounts = reinterpret_cast<int32_t *>(dout + lay.counts);
+        uint32_t *dbits = reinterpret_cast<uint32_t *>(dout + lay.bits);
         if (rc == GRIM_OK)
-            rc = grim_filter_batch(idx, &b, dcounts, dbits, d + lay.ws, lay.ws_bytes, nullptr,
-                                   slot->stream);
-        if (rc == GRIM_OK &&
-            hipMemcpyAsync(h + lay.out_base, d + lay.out_base, lay.out_bytes, hipMemcpyDeviceToHost,
-                           slot->stream) != hipSuccess)
-            rc = GRIM_E_HIP;
-        if (rc == GRIM_OK && hipEventRecord(slot->done, slot->stream) != hipSuccess)
-            rc = GRIM_E_HIP;
+            rc = grim_filter_batch(idx, &b, dcounts, dbits, d + lay.ws, lay.ws_bytes, nullptr, st);
+        // results: large count slices straight into the request's block, the
+        // rest (small slices, all pass bits, the status word) via the stage
+        if (rc == GRIM_OK) {
+            uint64_t run_lo = 0, run_hi = 0;
+            bool run = false;
+            auto flush = [&] {
+                if (run && e == hipSuccess)
+                    e = hipMemcpyAsync(hout + run_lo, dout + run_lo, run_hi - run_lo,
+                                       hipMemcpyDeviceToHost, st);
+                run = false;
+            };
+            for (size_t j = 0; j < take.size() && e == hipSuccess; ++j) {
+                Request &r = *take[j];
+                const uint64_t lo = lay.counts + slot->pair_base[j] * 4, nb = r.n_pairs * 4;
+                if (nb >= kDirectBytes) {
+                    flush();
+                    e = hipMemcpyAsync(r.counts(), dout + lo, nb, hipMemcpyDeviceToHost, st);
+                    slot->counts_direct[j] = 1;
+                } else if (nb) {
+                    if (run && lo == run_hi) {
+                        run_hi = lo + nb;
+                    } else {
+                        flush();
+                        run = true;
+                        run_lo = lo;
+                        run_hi = lo + nb;
+                    }
+                }
+            }
+            flush();
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(hout + lay.bits, dout + lay.bits, ((pbase + 31) / 32) * 4 + 4,
+                                   hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess)  // status word of this launch
+                e = hipMemcpyAsync(hout + lay.status, d + lay.ws, 4, hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess)
+                e = hipEventRecord(slot->done, st);
+            if (e != hipSuccess)
+                rc = GRIM_E_HIP;
+        }
     }
-    slot->t_launch = Clock::now();
     lk.lock();
     if (rc != GRIM_OK) {
-        // the tick never reached the device: fail its requests
+        // the tick never completed on the device: fail its requests
         (void)hipStreamSynchronize(slot->stream);
         const auto t = Clock::now();
         for (auto &r : take) {
@@ -484,6 +648,15 @@ extern "C" int grim_serve_create(const grim_index_t *idx, const grim_serve_cfg_t
     if (hipMalloc(reinterpret_cast<void **>(&s->pool_base), c.hbm_budget_bytes) != hipSuccess)
         return GRIM_E_NOMEM;
     s->pool = std::make_unique<Pool>(c.hbm_budget_bytes);
+    // pinned arena for request blocks: as large as the device budget, at most 4 GiB
+    s->arena_bytes = std::min<uint64_t>(std::max<uint64_t>(c.hbm_budget_bytes, 64ull << 20),
+                                        4ull << 30);
+    if (hipHostMalloc(reinterpret_cast<void **>(&s->arena), s->arena_bytes, hipHostMallocDefault) !=
+        hipSuccess) {
+        s->arena = nullptr;
+        s->arena_bytes = 0;
+    }
+    s->arena_pool = std::make_unique<Pool>(s->arena_bytes);
     s->slots.resize(c.n_streams);
     for (auto &sl : s->slots) {
         if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
@@ -494,6 +667,8 @@ extern "C" int grim_serve_create(const grim_index_t *idx, const grim_serve_cfg_t
                 if (x.done)
                     (void)hipEventDestroy(x.done);
             }
+            if (s->arena)
+                (void)hipHostFree(s->arena);
             (void)hipFree(s->pool_base);
             return GRIM_E_HIP;
         }
@@ -506,6 +681,7 @@ extern "C" int grim_serve_create(const grim_index_t *idx, const grim_serve_cfg_t
 
 extern "C" int grim_serve_submit(grim_server_t *s, const grim_batch_t *b, uint64_t *ticket)
 {
+    const auto t0 = Clock::now();
     if (!s || !b || !ticket || b->e_den == 0)
         return GRIM_E_INVALID;
     if (b->max_len > s->cfg.max_len)
@@ -514,42 +690,59 @@ extern "C" int grim_serve_submit(grim_server_t *s, const grim_batch_t *b, uint64
     if ((n && (!b->read_off || !b->read_len || !b->read_e || !b->cand_off || !b->reads_2bit)) ||
         (P && !b->cand_bin) || (!n && P))
         return GRIM_E_INVALID;
-    auto r = std::make_shared<Request>();
-    try {
-        r->words.assign(b->reads_2bit, b->reads_2bit + (n ? b->n_read_words : 0));
-        r->read_off.assign(b->read_off, b->read_off + n);
-        r->read_len.assign(b->read_len, b->read_len + n);
-        r->read_e.assign(b->read_e, b->read_e + n);
-        if (n)
-            r->cand_off.assign(b->cand_off, b->cand_off + n + 1);
-        else
-            r->cand_off.assign(1, 0);
-        r->cand_bin.assign(b->cand_bin, b->cand_bin + P);
-    } catch (...) {
-        return GRIM_E_NOMEM;
-    }
-    // validate on the host: a request that is malformed never reaches the device
-    if (r->cand_off[0] != 0 || r->cand_off[n] != P)
-        return GRIM_E_INVALID;
-    const uint64_t nbases = (uint64_t)r->words.size() * 16;
-    for (uint64_t i = 0; i < n; ++i) {
-        if (r->cand_off[i + 1] < r->cand_off[i])
+    // validate on the host: a malformed request never reaches the device
+    const uint64_t nwords = n ? b->n_read_words : 0;
+    if (n) {
+        if (b->cand_off[0] != 0 || b->cand_off[n] != P)
             return GRIM_E_INVALID;
-        if (r->read_len[i] > b->max_len || r->read_off[i] > nbases ||
-            r->read_len[i] > nbases - r->read_off[i])
-            return GRIM_E_READ;
+        const uint64_t nbases = nwords * 16;
+        for (uint64_t i = 0; i < n; ++i) {
+            if (b->cand_off[i + 1] < b->cand_off[i])
+                return GRIM_E_INVALID;
+            if (b->read_len[i] > b->max_len || b->read_off[i] > nbases ||
+                b->read_len[i] > nbases - b->read_off[i])
+                return GRIM_E_READ;
+        }
     }
+    if (plan(nwords + 1, n, P, ws_need(s->idx, P)).total > s->cfg.hbm_budget_bytes)
+        return GRIM_E_BUDGET;
+    auto r = std::make_shared<Request>();
+    r->lay = req_layout(nwords, n, P);
+    {
+        std::lock_guard<std::mutex> lk(s->arena_mu);
+        uint64_t off = 0;
+        if (s->arena && s->arena_pool->alloc(r->lay.total, &off)) {
+            r->host = s->arena + off;
+            r->arena_off = off;
+            r->pinned = true;
+        }
+    }
+    if (!r->host) {
+        r->host = static_cast<uint8_t *>(std::aligned_alloc(256, r->lay.total));
+        if (!r->host)
+            return GRIM_E_NOMEM;
+    }
+    par_memcpy(r->words(), b->reads_2bit, nwords * 4);
+    if (n) {
+        std::memcpy(r->read_off(), b->read_off, n * 8);
+        std::memcpy(r->read_len(), b->read_len, n * 4);
+        std::memcpy(r->read_e(), b->read_e, n * 4);
+        std::memcpy(r->cand_off(), b->cand_off, (n + 1) * 8);
+    } else {
+        r->cand_off()[0] = 0;
+    }
+    par_memcpy(r->cand_bin(), b->cand_bin, P * 4);
     r->e_den = b->e_den;
+    r->n_words = nwords;
     r->n_reads = n;
     r->n_pairs = P;
-    const uint64_t need = plan(r->words.size() + 1, n, P, ws_need(s->idx, P)).total;
-    if (need > s->cfg.hbm_budget_bytes)
-        return GRIM_E_BUDGET;
-    r->t_submit = Clock::now();
+    r->t_submit = t0;
     {
         std::lock_guard<std::mutex> lk(s->mu);
-        if (s->stop)
+        if (s->stop) {
+            s->free_block(*r);
             return GRIM_E_INVALID;
+        }
         r->ticket = s->next_ticket++;
         s->all[r->ticket] = r;
         s->queue.push_back(r);
@@ -560,20 +753,25 @@ extern "C" int grim_serve_submit(grim_server_t *s, const grim_batch_t *b, uint64
     return GRIM_OK;
 }
 
-static int finish(grim_server_t *s, std::map<uint64_t, std::shared_ptr<Request>>::iterator it,
-                  int32_t *counts, uint32_t *pass_bits, grim_req_stats_t *st)
+// Hand a finished request's results to the caller.  Called with the server
+// lock held; releases it before copying so the scheduler is not stalled.
+static int finish(grim_server_t *s, std::unique_lock<std::mutex> &lk,
+                  std::map<uint64_t, std::shared_ptr<Request>>::iterator it, int32_t *counts,
+                  uint32_t *pass_bits, grim_req_stats_t *st)
 {
-    Request &r = *it->second;
-    if (r.status == GRIM_OK || r.status == GRIM_E_BIN_RANGE) {
-        if (counts && !r.counts.empty())
-            std::memcpy(counts, r.counts.data(), r.counts.size() * 4);
-        if (pass_bits && !r.bits.empty())
-            std::memcpy(pass_bits, r.bits.data(), r.bits.size() * 4);
+    std::shared_ptr<Request> rp = it->second;
+    Request &r = *rp;
+    s->all.erase(it);
+    lk.unlock();
+    if ((r.status == GRIM_OK || r.status == GRIM_E_BIN_RANGE) && r.host) {
+        if (counts)
+            par_memcpy(counts, r.counts(), r.n_pairs * 4);
+        if (pass_bits)
+            std::memcpy(pass_bits, r.bits(), ((r.n_pairs + 31) / 32) * 4);
     }
     if (st) {
-        st->queue_ms = r.state == State::Done && r.t_admit.time_since_epoch().count()
-                           ? ms_between(r.t_submit, r.t_admit)
-                           : 0.0;
+        st->queue_ms = r.t_admit.time_since_epoch().count() ? ms_between(r.t_submit, r.t_admit)
+                                                            : 0.0;
         st->latency_ms = ms_between(r.t_submit, r.t_done);
         st->n_pairs = r.n_pairs;
         st->tick = r.tick;
@@ -581,7 +779,7 @@ static int finish(grim_server_t *s, std::map<uint64_t, std::shared_ptr<Request>>
         st->status = r.status;
     }
     const int rc = r.status;
-    s->all.erase(it);
+    s->free_block(r);
     return rc;
 }
 
@@ -590,13 +788,13 @@ extern "C" int grim_serve_poll(grim_server_t *s, uint64_t ticket, int32_t *count
 {
     if (!s)
         return GRIM_E_INVALID;
-    std::lock_guard<std::mutex> lk(s->mu);
+    std::unique_lock<std::mutex> lk(s->mu);
     auto it = s->all.find(ticket);
     if (it == s->all.end())
         return GRIM_E_INVALID;
     if (it->second->state != State::Done)
         return GRIM_PENDING;
-    return finish(s, it, counts, pass_bits, st);
+    return finish(s, lk, it, counts, pass_bits, st);
 }
 
 extern "C" int grim_serve_wait(grim_server_t *s, uint64_t ticket, int64_t timeout_ms,
@@ -617,7 +815,7 @@ extern "C" int grim_serve_wait(grim_server_t *s, uint64_t ticket, int64_t timeou
     it = s->all.find(ticket);
     if (it == s->all.end())
         return GRIM_E_INVALID;
-    return finish(s, it, counts, pass_bits, st);
+    return finish(s, lk, it, counts, pass_bits, st);
 }
 
 extern "C" int grim_serve_cancel(grim_server_t *s, uint64_t ticket)
@@ -709,13 +907,18 @@ extern "C" void grim_serve_destroy(grim_server_t *s)
     s->cv_work.notify_all();
     if (s->thr.joinable())
         s->thr.join();
+    for (auto &kv : s->all)
+        s->free_block(*kv.second);
+    s->all.clear();
     for (auto &sl : s->slots) {
         (void)hipStreamSynchronize(sl.stream);
-        if (sl.pinned)
-            (void)hipHostFree(sl.pinned);
+        if (sl.stage)
+            (void)hipHostFree(sl.stage);
         (void)hipEventDestroy(sl.done);
         (void)hipStreamDestroy(sl.stream);
     }
+    if (s->arena)
+        (void)hipHostFree(s->arena);
     (void)hipFree(s->pool_base);
     delete s;
 }
