@@ -251,6 +251,41 @@ int grim_verify_survivors(const grim_index_t *idx, const grim_batch_t *b,
                           const uint32_t *surv_read, const uint32_t *surv_bin,
                           uint64_t n_survivors, int32_t *dist, uint32_t *ok_bits, void *stream);
 
+/* ------------------------------------------------------------------- seeding */
+/* The step before the filter: the mapper looks up exact seeds of each read in a
+ * hash table of reference locations and sends the locations to GRIM-Filter
+ * (Section "Introduction", Fig. 1; Section "Integration with a Full Read
+ * Mapper").  Here the table is a k-mer position index built on the GPU. */
+typedef struct grim_seed_index grim_seed_index_t;  /* opaque, device-resident */
+typedef struct grim_candidates grim_candidates_t;  /* opaque, device-resident */
+
+/* Index every k-mer (4 <= k <= 15) of a reference of ref_len <= 2^32 - 1 bases
+ * (host ref_2bit, grim_packed_words(ref_len) words).  Synchronous; the index
+ * (4^k + 1 u64 offsets and ref_len - k + 1 u32 positions) stays on the current
+ * device until grim_seed_index_free. */
+int grim_seed_index_build(const uint32_t *ref_2bit, uint64_t ref_len, uint32_t k,
+                          grim_seed_index_t **out, void *stream);
+void grim_seed_index_free(grim_seed_index_t *si);
+
+/* Candidate bins of a batch of reads (uses reads_2bit, n_read_words, read_off,
+ * read_len, n_reads of *reads; device memory): seeds are each read's k-mers at
+ * offsets 0, k, 2k, ... while the seed fits; every occurrence p of the seed at
+ * offset o proposes location z = p - o clamped into [0, G - 1] and bin
+ * z / bin_stride; a read's bins are deduplicated, sorted increasingly and cut
+ * to the first `cap`.  Reads outside the packed buffer get no candidates.
+ * Synchronous; allocates the result (CSR offsets n_reads + 1 u64, bins u32) on
+ * the device.  GRIM_E_UNSUPPORTED beyond 2^31 - 1 seed hits or reads. */
+int grim_seed_candidates(const grim_seed_index_t *si, const grim_batch_t *reads,
+                         uint64_t bin_stride, uint32_t cap, grim_candidates_t **out, void *stream);
+
+/* Sizes and device pointers of a candidate list (any output may be NULL). */
+int grim_candidates_info(const grim_candidates_t *c, uint64_t *n_reads, uint64_t *n_pairs,
+                         const uint64_t **cand_off, const uint32_t **cand_bin);
+/* Copy a candidate list to host memory (cand_off: n_reads + 1, cand_bin: n_pairs). */
+int grim_candidates_copy_to_host(const grim_candidates_t *c, uint64_t *cand_off,
+                                 uint32_t *cand_bin);
+void grim_candidates_free(grim_candidates_t *c);
+
 /* ---------------------------------------------------------------- HIP graphs */
 /* Capture the work-list and filter kernels of one grim_filter_batch call (same
  * arguments, fixed buffers) into a HIP graph; replay it with grim_graph_launch

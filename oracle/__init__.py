@@ -56,6 +56,8 @@ class Oracle:
             "oracle_pack_bitmask": (None, [_u8p, u64, _u32p]),
             "oracle_edit_distance_in_bin": (ctypes.c_int32, [_u8p, u64, u64, u64, u64, _u8p, u32,
                                                              _i32p]),
+            "oracle_seed_candidates": (u64, [_u8p, u64, u32, _u8p, _u64p, _u32p, u64, u64, u32,
+                                             _u32p, _u64p, _u32p]),
             "oracle_survivors": (u64, [_u32p, u64, _u64p, u64, _u32p, u64, _u64p, _u32p, _u32p]),
         }
         for name, (res, args) in sig.items():
@@ -193,6 +195,25 @@ class Oracle:
             d[i] = min(dist, E + 1)
         return d
 
+    def seed_candidates(self, ref, k, read_codes, read_off, read_len, B, cap):
+        """Candidate bins from exact k-mer seeds: (cand_off u64[n+1], cand_bin u32)."""
+        ref = _c(ref, np.uint8)
+        read_codes = _c(read_codes if len(read_codes) else np.zeros(1, np.uint8), np.uint8)
+        read_off = _c(read_off, np.uint64)
+        read_len = _c(read_len, np.uint32)
+        n = read_len.size
+        cnt = np.zeros(max(1, n), dtype=np.uint32)
+        self.lib.oracle_seed_candidates(_ptr(ref, _u8p), ref.size, k, _ptr(read_codes, _u8p),
+                                        _ptr(read_off, _u64p), _ptr(read_len, _u32p), n, B, cap,
+                                        _ptr(cnt, _u32p), None, None)
+        off = np.zeros(n + 1, dtype=np.uint64)
+        np.cumsum(cnt[:n], out=off[1:])
+        bins = np.zeros(max(1, int(off[-1])), dtype=np.uint32)
+        self.lib.oracle_seed_candidates(_ptr(ref, _u8p), ref.size, k, _ptr(read_codes, _u8p),
+                                        _ptr(read_off, _u64p), _ptr(read_len, _u32p), n, B, cap,
+                                        _ptr(cnt, _u32p), _ptr(off, _u64p), _ptr(bins, _u32p))
+        return off, bins[:int(off[-1])]
+
 
 def _default():
     global _lib
@@ -222,7 +243,7 @@ def _fwd(name):
 
 for _n in ("num_bins", "vector_bytes", "token", "max_edits", "num_tokens", "threshold",
            "build_bin", "build_index", "count", "filter_batch", "pack_bitmask", "survivors",
-           "edit_distance_in_bin", "verify"):
+           "edit_distance_in_bin", "verify", "seed_candidates"):
     globals()[_n] = _fwd(_n)
 
 

@@ -259,3 +259,98 @@ int32_t oracle_edit_distance_in_bin(const uint8_t *ref, uint64_t G, uint64_t B, 
             m = row[j];
     return m;
 }
+
+/* Seeding, the step before the filter (Section "Introduction", Fig. 1: the
+ * mapper looks up short exact seeds of the read in a hash table of reference
+ * locations; Section "Integration with a Full Read Mapper": those locations
+ * are what GRIM-Filter receives).  Seeds are the read's k-mers at offsets
+ * 0, k, 2k, ... (while the seed fits); every reference occurrence p of the seed
+ * at offset o proposes location z = p - o, clamped into [0, G - 1], and bin
+ * z / B.  Per read the bins are deduplicated, sorted increasingly and cut to
+ * the first `cap`.  The reference k-mer table is built plainly: every
+ * (k-mer, position) pair, sorted.  Writes n_cand[r] for every read and, when
+ * `bins` is not NULL, the bins of read r at bins[out_off[r]].  Returns the total
+ * number of candidates. */
+typedef struct {
+    uint64_t kmer;
+    uint64_t pos;
+} oracle_kp;
+
+static int oracle_kp_cmp(const void *a, const void *b)
+{
+    const oracle_kp *x = (const oracle_kp *)a, *y = (const oracle_kp *)b;
+    if (x->kmer != y->kmer)
+        return x->kmer < y->kmer ? -1 : 1;
+    return x->pos < y->pos ? -1 : (x->pos > y->pos);
+}
+
+static int oracle_u64_cmp(const void *a, const void *b)
+{
+    uint64_t x = *(const uint64_t *)a, y = *(const uint64_t *)b;
+    return x < y ? -1 : (x > y);
+}
+
+#include <stdlib.h>
+
+uint64_t oracle_seed_candidates(const uint8_t *ref, uint64_t G, uint32_t k,
+                                const uint8_t *read_codes, const uint64_t *read_off,
+                                const uint32_t *read_len, uint64_t n_reads, uint64_t B,
+                                uint32_t cap, uint32_t *n_cand, const uint64_t *out_off,
+                                uint32_t *bins)
+{
+    uint64_t n_kp = G >= k ? G - k + 1 : 0;
+    oracle_kp *table = (oracle_kp *)malloc(sizeof(oracle_kp) * (n_kp ? n_kp : 1));
+    for (uint64_t p = 0; p < n_kp; p++) {
+        table[p].kmer = oracle_token(ref + p, k);
+        table[p].pos = p;
+    }
+    qsort(table, n_kp, sizeof(oracle_kp), oracle_kp_cmp);
+    uint64_t total = 0;
+    uint64_t bufcap = 1024;
+    uint64_t *buf = (uint64_t *)malloc(sizeof(uint64_t) * bufcap);
+    for (uint64_t r = 0; r < n_reads; r++) {
+        const uint8_t *read = read_codes + read_off[r];
+        uint32_t L = read_len[r];
+        uint64_t n = 0;
+        for (uint32_t o = 0; o + k <= L; o += k) {
+            uint64_t km = oracle_token(read + o, k);
+            /* first table entry with kmer >= km */
+            uint64_t lo = 0, hi = n_kp;
+            while (lo < hi) {
+                uint64_t mid = (lo + hi) / 2;
+                if (table[mid].kmer < km)
+                    lo = mid + 1;
+                else
+                    hi = mid;
+            }
+            for (uint64_t h = lo; h < n_kp && table[h].kmer == km; h++) {
+                int64_t z = (int64_t)table[h].pos - (int64_t)o;
+                if (z < 0)
+                    z = 0;
+                if ((uint64_t)z > G - 1)
+                    z = (int64_t)(G - 1);
+                if (n == bufcap) {
+                    bufcap *= 2;
+                    buf = (uint64_t *)realloc(buf, sizeof(uint64_t) * bufcap);
+                }
+                buf[n++] = (uint64_t)z / B;
+            }
+        }
+        qsort(buf, n, sizeof(uint64_t), oracle_u64_cmp);
+        uint64_t u = 0;
+        for (uint64_t i = 0; i < n; i++) {
+            if (i > 0 && buf[i] == buf[i - 1])
+                continue;
+            if (u < cap && bins)
+                bins[out_off[r] + u] = (uint32_t)buf[i];
+            u++;
+        }
+        if (u > cap)
+            u = cap;
+        n_cand[r] = (uint32_t)u;
+        total += u;
+    }
+    free(buf);
+    free(table);
+    return total;
+}

@@ -136,6 +136,12 @@ _SIGS = {
     "grim_index_attach_reference": (ctypes.c_int, [_vp, _vp, _u64, _vp]),
     "grim_verify_survivors": (ctypes.c_int, [_vp, _P(grim_batch_t), _vp, _vp, _u64, _vp, _vp,
                                              _vp]),
+    "grim_seed_index_build": (ctypes.c_int, [_vp, _u64, _u32, _P(_vp), _vp]),
+    "grim_seed_index_free": (None, [_vp]),
+    "grim_seed_candidates": (ctypes.c_int, [_vp, _P(grim_batch_t), _u64, _u32, _P(_vp), _vp]),
+    "grim_candidates_info": (ctypes.c_int, [_vp, _P(_u64), _P(_u64), _P(_vp), _P(_vp)]),
+    "grim_candidates_copy_to_host": (ctypes.c_int, [_vp, _vp, _vp]),
+    "grim_candidates_free": (None, [_vp]),
     "grim_graph_create": (ctypes.c_int, [_vp, _P(grim_batch_t), _vp, _vp, _vp, _u64,
                                          _P(grim_tuning_t), _P(_vp)]),
     "grim_graph_launch": (ctypes.c_int, [_vp, _vp]),
@@ -442,6 +448,88 @@ def grim_verify_survivors(index, batch, surv_read, surv_bin, n=None, stream=None
                                       _ptr(surv_bin), n, _ptr(dist), _ptr(ok), _stream(stream)),
            "grim_verify_survivors")
     return dist[:n], ok[:(n + 31) // 32]
+
+
+class SeedIndex:
+    """Device k-mer position index of a reference (owns a grim_seed_index_t)."""
+
+    def __init__(self, ref, k=12, stream=None):
+        words = grim_pack_bases(ref)
+        self.k = int(k)
+        self.G = int(np.asarray(ref).size)
+        self._h = ctypes.c_void_p()
+        _check(_lib.grim_seed_index_build(words.ctypes.data_as(_vp), self.G, self.k,
+                                          ctypes.byref(self._h), _stream(stream)),
+               "grim_seed_index_build")
+
+    @property
+    def handle(self):
+        return self._h
+
+    def free(self):
+        if self._h is not None and self._h.value:
+            _lib.grim_seed_index_free(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Candidates:
+    """A device candidate list (owns a grim_candidates_t)."""
+
+    def __init__(self, handle):
+        self._h = handle
+        nr, npairs = _u64(), _u64()
+        po, pb = ctypes.c_void_p(), ctypes.c_void_p()
+        _check(_lib.grim_candidates_info(self._h, ctypes.byref(nr), ctypes.byref(npairs),
+                                         ctypes.byref(po), ctypes.byref(pb)), "grim_candidates_info")
+        self.n_reads, self.n_pairs = int(nr.value), int(npairs.value)
+        self.cand_off_ptr, self.cand_bin_ptr = po.value, pb.value
+
+    def to_host(self):
+        """(cand_off u64[n_reads+1], cand_bin u32[n_pairs]) copied to the host."""
+        off = np.empty(self.n_reads + 1, dtype=np.uint64)
+        bins = np.empty(max(1, self.n_pairs), dtype=np.uint32)
+        _check(_lib.grim_candidates_copy_to_host(self._h, off.ctypes.data_as(_vp),
+                                                 bins.ctypes.data_as(_vp)),
+               "grim_candidates_copy_to_host")
+        return off, bins[:self.n_pairs]
+
+    def free(self):
+        if self._h is not None and self._h.value:
+            _lib.grim_candidates_free(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def grim_seed_candidates(seed_index, batch, bin_stride, cap=4096, stream=None):
+    """Candidate bins of the batch's reads from exact k-mer seeds (device)."""
+    h = ctypes.c_void_p()
+    _check(_lib.grim_seed_candidates(seed_index.handle, ctypes.byref(batch.c), int(bin_stride),
+                                     int(cap), ctypes.byref(h), _stream(stream)),
+           "grim_seed_candidates")
+    return Candidates(h)
+
+
+def batch_with_candidates(batch, cands):
+    """A copy of `batch`'s grim_batch_t whose candidates are `cands` (device)."""
+    b = Batch.__new__(Batch)
+    b.__dict__.update(batch.__dict__)
+    b._cands = cands
+    b.n_pairs = cands.n_pairs
+    b.c = grim_batch_t(batch.c.reads_2bit, batch.c.n_read_words, batch.c.read_off,
+                       batch.c.read_len, batch.c.read_e, batch.c.e_den, batch.c.max_len,
+                       cands.cand_off_ptr, cands.cand_bin_ptr, batch.c.n_reads, cands.n_pairs)
+    return b
 
 
 class Graph:

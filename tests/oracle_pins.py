@@ -424,6 +424,46 @@ def check_edit_distance_in_bin(orc):
         assert got == want, (ref_s, B, O, b, read, got, want)
 
 
+def check_seed_candidates(orc):
+    """Seeding before the filter (Section 'Introduction', Fig. 1): bins of the
+    locations of exact k-mer seeds at read offsets 0, k, 2k, ... -- against a
+    plain substring scan of the reference, with dedup, order and cap."""
+    rng = random.Random(23)
+    for trial in range(40):
+        G = rng.randrange(20, 600)
+        alpha = "ACGT" if trial % 4 else "AC"
+        ref_s = "".join(rng.choice(alpha) for _ in range(G))
+        k = rng.randrange(2, 7)
+        B = rng.randrange(3, 50)
+        cap = rng.choice([1, 3, 1000])
+        reads = []
+        for _ in range(8):
+            if rng.random() < 0.6 and G > 30:
+                st = rng.randrange(0, G - 25)
+                r = list(ref_s[st:st + rng.randrange(0, 25)])
+                if r and rng.random() < 0.5:
+                    r[rng.randrange(len(r))] = rng.choice("ACGT")
+                reads.append("".join(r))
+            else:
+                reads.append("".join(rng.choice(alpha) for _ in range(rng.randrange(0, 20))))
+        want = []
+        for rs in reads:
+            bins = set()
+            for o in range(0, len(rs) - k + 1, k):
+                seed = rs[o:o + k]
+                for p in range(0, G - k + 1):
+                    if ref_s[p:p + k] == seed:
+                        z = min(max(p - o, 0), G - 1)
+                        bins.add(z // B)
+            want.append(sorted(bins)[:cap])
+        codes = np.concatenate([enc(r) for r in reads] + [np.zeros(0, np.uint8)])
+        lens = np.array([len(r) for r in reads], dtype=np.uint32)
+        offs = np.concatenate([[0], np.cumsum(lens)[:-1]]).astype(np.uint64)
+        off, bins = orc.seed_candidates(enc(ref_s), k, codes, offs, lens, B, cap)
+        got = [bins[int(off[i]):int(off[i + 1])].tolist() for i in range(len(reads))]
+        assert got == want, (trial, got, want)
+
+
 ALL_CHECKS = [
     check_golden_hand_vectors,
     check_all_a_example,
@@ -440,4 +480,5 @@ ALL_CHECKS = [
     check_bitmask_packing,
     check_survivor_list,
     check_edit_distance_in_bin,
+    check_seed_candidates,
 ]

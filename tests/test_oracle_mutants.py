@@ -49,6 +49,9 @@ MUTANTS = {
                                  "int32_t sub = diag;"),
     "verify_last_column_only": ("    int32_t m = row[0];\n    for (uint64_t j = 1; j <= n; j++)\n        if (row[j] < m)\n            m = row[j];",
                                 "    int32_t m = row[n];"),
+    "seed_no_clamp_low": ("                if (z < 0)\n                    z = 0;", "                if (z < 0)\n                    z = -z;"),
+    "seed_step_one": ("for (uint32_t o = 0; o + k <= L; o += k) {", "for (uint32_t o = 0; o + k <= L; o += 1) {"),
+    "seed_no_dedup": ("            if (i > 0 && buf[i] == buf[i - 1])\n                continue;", ""),
     "bin_wrong_vector": ("const uint8_t *vec = index + b * nbytes;     /* step 2 */",
                          "const uint8_t *vec = index + (b ^ 1) % n_bins * nbytes;"),
 }
