@@ -157,6 +157,64 @@ def serving_leg(g, idx, w, rng, loads=(0.25, 0.5, 0.75), seconds=2.5, max_reads=
     return out
 
 
+def window_leg(g, idx, w, torch, stream, rng, window_bins=4096, n_reads=200_000):
+    """The bin-window form: each of n_reads reads against the window_bins
+    consecutive bins around its true bin, from the token-major index copy.
+    Compared with the batched random-gather kernel on the same explicit pairs
+    (identical outputs checked) and timed with HIP events."""
+    n_reads = min(n_reads, w["read_len"].size)
+    n_bins = idx.n_bins
+    tb = (w["read_z"][:n_reads] // w["B"]).astype(np.int64)
+    lo = np.clip(tb - window_bins // 2, 0, n_bins - window_bins).astype(np.uint32)
+    off = np.arange(n_reads + 1, dtype=np.uint64) * window_bins
+    o_end = int(w["read_off"][n_reads - 1]) + int(w["read_len"][n_reads - 1])
+    t0 = time.time()
+    idx.transpose()
+    torch.cuda.synchronize()
+    t_transpose = time.time() - t0
+    wb = g.Batch(w["codes"][:o_end], w["read_off"][:n_reads], w["read_len"][:n_reads],
+                 w["read_e"][:n_reads], w["e_den"], off, np.zeros(1, np.uint32),
+                 max_len=int(w["read_len"].max()))
+    n = wb.n_pairs
+    wl = torch.from_numpy(lo.view(np.int32)).cuda()
+    c1, b1 = g.alloc_outputs(n)
+    ws = torch.zeros(256, dtype=torch.uint8, device="cuda")
+    g.grim_filter_windows(idx, wb, wl, c1, b1, ws)
+    rc, _ = g.grim_filter_status(ws)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(5):
+        g.grim_filter_windows(idx, wb, wl, c1, b1, ws)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 5
+    # the same pairs as explicit candidates through the batched kernel
+    cb = (lo.astype(np.int64)[:, None] + np.arange(window_bins)[None, :]).astype(np.uint32).ravel()
+    eb = g.Batch(w["codes"][:o_end], w["read_off"][:n_reads], w["read_len"][:n_reads],
+                 w["read_e"][:n_reads], w["e_den"], off, cb, max_len=int(w["read_len"].max()))
+    del cb
+    c2, b2 = g.alloc_outputs(n)
+    ws2 = g.alloc_workspace(idx, n)
+    g.grim_filter_batch(idx, eb, c2, b2, ws2)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(3):
+        g.grim_filter_batch(idx, eb, c2, b2, ws2)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_batched = e0.elapsed_time(e1) / 3
+    same = bool(torch.equal(c1[:n], c2[:n]) and torch.equal(b1[:(n + 31) // 32], b2[:(n + 31) // 32]))
+    ntok = float(np.mean(np.maximum(w["read_len"][:n_reads].astype(np.int64) - w["q"] + 1, 0)))
+    row_bytes = ntok * window_bins / 8 + window_bins * (4 + 1 / 8)
+    out = dict(window_bins=window_bins, reads=n_reads, pairs=n, ms=ms, pairs_per_s=n / (ms * 1e-3),
+               status=rc, identical=same, batched_same_pairs_ms=ms_batched,
+               speedup_vs_batched_same_pairs=ms_batched / ms, transpose_s=t_transpose,
+               algorithmic_bytes_per_window=row_bytes,
+               algorithmic_gbs=n_reads * row_bytes / (ms * 1e-3) / 1e9)
+    del c1, b1, c2, b2, ws2, wb, eb
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -177,6 +235,7 @@ def main():
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--wg", type=int, default=0)
     ap.add_argument("--cpu-pairs", type=float, default=3.0e8)
+    ap.add_argument("--no-window", action="store_true", help="skip the bin-window leg")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
     args = ap.parse_args()
 
@@ -368,6 +427,13 @@ def main():
         del dist, okb
     del sp, sr, sb
 
+    window = None
+    if args.config == "batched" and not args.no_window:
+        window = window_leg(g, idx, w, torch, stream, rng)
+        log(f"[bench] bin windows ({window['window_bins']} bins): {window['pairs']} pairs in "
+            f"{window['ms']:.3f} ms -> {window['pairs_per_s']:.3e} pairs/s "
+            f"(batched random-gather form: {pairs_per_s:.3e}); identical={window['identical']}")
+
     check_n, check_bad = sample_check(w, counts, bits, 2000, rng)
     log(f"[bench] sampled parity: {check_bad} mismatches in {check_n} pairs")
 
@@ -441,6 +507,7 @@ def main():
         "plain_kernel": plain,
         "seed_location_checker": checker,
         "seeding": seeding,
+        "bin_window": window,
         "sampled_parity": {"pairs": check_n, "mismatches": check_bad},
         "serving": serving,
         "cpu_baseline": cpu,

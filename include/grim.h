@@ -251,6 +251,30 @@ int grim_verify_survivors(const grim_index_t *idx, const grim_batch_t *b,
                           const uint32_t *surv_read, const uint32_t *surv_bin,
                           uint64_t n_survivors, int32_t *dist, uint32_t *ok_bits, void *stream);
 
+/* --------------------------------------------------------------- bin windows */
+/* The paper's bin-window form (Section "Mapping GRIM-Filter to 3D-Stacked
+ * Memory with PIM": the mapper sends a read with a range of consecutive bins,
+ * and the bitvectors are stored token-major so that one access returns one
+ * token's existence bits for many bins; Section "GRIM-Filter Parallelization":
+ * a window of consecutive bins is filtered together).
+ *
+ * grim_index_transpose builds the token-major copy on the index's device (as
+ * many bytes again as the vectors): row t holds, for every bin b, bit
+ * (b & 31) of word b >> 5 = "token t occurs in bin b".  Synchronous. */
+int grim_index_transpose(grim_index_t *idx, void *stream);
+
+/* Filter every bin of each read's window: read r's window is bins
+ * [win_lo[r], win_lo[r] + (cand_off[r+1] - cand_off[r])), and pair
+ * cand_off[r] + j is bin win_lo[r] + j (b->cand_bin is not used).  Outputs,
+ * status and errors as grim_filter_batch (a bin >= n_bins gives -1 and
+ * GRIM_FLAG_BIN_RANGE).  win_lo: device u32[n_reads].  workspace: device,
+ * >= 256 bytes, 256-byte aligned.  Needs grim_index_transpose first
+ * (else GRIM_E_INVALID); b->max_len <= 4096 (else GRIM_E_UNSUPPORTED).
+ * Asynchronous on `stream`; allocates nothing. */
+int grim_filter_windows(const grim_index_t *idx, const grim_batch_t *b, const uint32_t *win_lo,
+                        int32_t *counts, uint32_t *pass_bits, void *workspace,
+                        uint64_t workspace_bytes, void *stream);
+
 /* ------------------------------------------------------------------- seeding */
 /* The step before the filter: the mapper looks up exact seeds of each read in a
  * hash table of reference locations and sends the locations to GRIM-Filter

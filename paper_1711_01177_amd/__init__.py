@@ -136,6 +136,8 @@ _SIGS = {
     "grim_index_attach_reference": (ctypes.c_int, [_vp, _vp, _u64, _vp]),
     "grim_verify_survivors": (ctypes.c_int, [_vp, _P(grim_batch_t), _vp, _vp, _u64, _vp, _vp,
                                              _vp]),
+    "grim_index_transpose": (ctypes.c_int, [_vp, _vp]),
+    "grim_filter_windows": (ctypes.c_int, [_vp, _P(grim_batch_t), _vp, _vp, _vp, _vp, _u64, _vp]),
     "grim_seed_index_build": (ctypes.c_int, [_vp, _u64, _u32, _P(_vp), _vp]),
     "grim_seed_index_free": (None, [_vp]),
     "grim_seed_candidates": (ctypes.c_int, [_vp, _P(grim_batch_t), _u64, _u32, _P(_vp), _vp]),
@@ -279,6 +281,10 @@ class Index:
         _check(_lib.grim_index_attach_reference(self._h, words.ctypes.data_as(_vp),
                                                 int(np.asarray(ref).size), _stream(stream)),
                "grim_index_attach_reference")
+
+    def transpose(self, stream=None):
+        """Build the token-major copy used by grim_filter_windows."""
+        _check(_lib.grim_index_transpose(self._h, _stream(stream)), "grim_index_transpose")
 
     def save(self, path):
         _check(_lib.grim_index_save(self._h, str(path).encode()), "grim_index_save")
@@ -448,6 +454,13 @@ def grim_verify_survivors(index, batch, surv_read, surv_bin, n=None, stream=None
                                       _ptr(surv_bin), n, _ptr(dist), _ptr(ok), _stream(stream)),
            "grim_verify_survivors")
     return dist[:n], ok[:(n + 31) // 32]
+
+
+def grim_filter_windows(index, batch, win_lo, counts, pass_bits, workspace, stream=None):
+    """Bin-window filter: every bin of [win_lo[r], win_lo[r] + window size)."""
+    _check(_lib.grim_filter_windows(index.handle, ctypes.byref(batch.c), _ptr(win_lo),
+                                    _ptr(counts), _ptr(pass_bits), _ptr(workspace),
+                                    workspace.numel(), _stream(stream)), "grim_filter_windows")
 
 
 class SeedIndex:

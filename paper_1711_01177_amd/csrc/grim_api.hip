@@ -329,6 +329,8 @@ extern "C" int grim_build_bins(const uint32_t *ref_2bit, uint64_t ref_len, const
         return GRIM_E_NOMEM;
     idx->d_ref = nullptr;
     idx->ref_words = 0;
+    idx->d_rows = nullptr;
+    idx->row_words = 0;
     idx->q = p->q;
     idx->device = dev;
     idx->B = p->bin_stride;
@@ -478,6 +480,8 @@ extern "C" int grim_index_load(const char *path, grim_index_t **out, void *strea
         return GRIM_E_NOMEM;
     idx->d_ref = nullptr;
     idx->ref_words = 0;
+    idx->d_rows = nullptr;
+    idx->row_words = 0;
     idx->q = h.q;
     idx->device = dev;
     idx->B = h.B;
@@ -509,6 +513,8 @@ extern "C" void grim_index_free(grim_index_t *idx)
         return;
     if (idx->d_ref)
         (void)hipFree(idx->d_ref);
+    if (idx->d_rows)
+        (void)hipFree(idx->d_rows);
     (void)hipFree(idx->d_vec);
     delete idx;
 }
@@ -790,6 +796,97 @@ extern "C" int grim_verify_survivors(const grim_index_t *idx, const grim_batch_t
     if (grid > cap)
         grid = cap;
     HIP_TRY(launch_verify(reinterpret_cast<hipStream_t>(stream), W, (uint32_t)grid, a));
+    return GRIM_OK;
+}
+
+// ---------------------------------------------------------------- bin windows
+extern "C" int grim_index_transpose(grim_index_t *idx, void *stream)
+{
+    if (!idx)
+        return GRIM_E_INVALID;
+    const uint64_t row_words = ((idx->n_bins + 63) / 64) * 2;
+    const uint64_t n_rows = 1ull << (2 * idx->q);
+    uint32_t *rows = nullptr;
+    if (hipMalloc(&rows, n_rows * row_words * 4) != hipSuccess)
+        return GRIM_E_NOMEM;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const uint64_t groups = (idx->n_bins + 63) / 64;
+    uint64_t grid = (groups + 3) / 4;
+    const uint64_t cap = (uint64_t)cu_count(idx->device) * 32;
+    if (grid > cap)
+        grid = cap;
+    hipError_t e = launch_transpose(s, idx->q, reinterpret_cast<const uint32_t *>(idx->d_vec),
+                                    idx->n_bins, row_words, rows, (uint32_t)grid);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        (void)hipFree(rows);
+        return hip_fail(e, "grim_index_transpose");
+    }
+    if (idx->d_rows)
+        (void)hipFree(idx->d_rows);
+    idx->d_rows = rows;
+    idx->row_words = row_words;
+    return GRIM_OK;
+}
+
+extern "C" int grim_filter_windows(const grim_index_t *idx, const grim_batch_t *b,
+                                   const uint32_t *win_lo, int32_t *counts, uint32_t *pass_bits,
+                                   void *workspace, uint64_t workspace_bytes, void *stream)
+{
+    if (!idx || !b)
+        return GRIM_E_INVALID;
+    if (b->e_den == 0 || b->max_len == 0 || (b->n_reads == 0 && b->n_pairs != 0))
+        return GRIM_E_INVALID;
+    if (b->max_len > 4096)
+        return GRIM_E_UNSUPPORTED;
+    if (b->n_reads && (!b->read_off || !b->read_len || !b->read_e || !b->cand_off || !win_lo ||
+                       !b->reads_2bit || b->n_read_words == 0))
+        return GRIM_E_INVALID;
+    if (b->n_pairs && (!counts || !pass_bits))
+        return GRIM_E_INVALID;
+    if (!idx->d_rows)
+        return GRIM_E_INVALID;
+    if (!workspace || workspace_bytes < kWsHeader || (reinterpret_cast<uintptr_t>(workspace) & 255))
+        return GRIM_E_INVALID;
+    int dev = -1;
+    int rc = current_device(&dev);
+    if (rc)
+        return rc;
+    if (dev != idx->device)
+        return GRIM_E_INVALID;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    WindowArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.rows = idx->d_rows;
+    a.row_words = idx->row_words;
+    a.n_bins = idx->n_bins;
+    a.rw = b->reads_2bit;
+    a.nw = b->n_read_words;
+    a.read_off = b->read_off;
+    a.read_len = b->read_len;
+    a.read_e = b->read_e;
+    a.e_den = b->e_den;
+    a.max_len = b->max_len;
+    a.cand_off = b->cand_off;
+    a.win_lo = win_lo;
+    a.n_reads = b->n_reads;
+    a.n_pairs = b->n_pairs;
+    a.counts = counts;
+    a.pass_bits = pass_bits;
+    a.status = reinterpret_cast<uint32_t *>(workspace);
+    a.counter = reinterpret_cast<uint32_t *>(workspace) + 1;
+    a.npl = planes_for(idx->q, b->max_len);
+    HIP_TRY(launch_zero(s, a.status, 2));
+    const uint64_t n_words = (b->n_pairs + 31) / 32;
+    if (n_words)
+        HIP_TRY(launch_zero(s, pass_bits, n_words));
+    if (b->n_reads == 0)
+        return GRIM_OK;
+    uint64_t grid = (uint64_t)cu_count(idx->device) * 4;
+    if (grid > b->n_reads)
+        grid = b->n_reads;
+    HIP_TRY(launch_window(s, idx->q, (uint32_t)grid, (size_t)b->max_len * 4, a));
     return GRIM_OK;
 }
 

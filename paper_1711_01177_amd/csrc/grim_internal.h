@@ -57,6 +57,28 @@ struct VerifyArgs {
     uint32_t *ok_bits;
 };
 
+// Arguments of the bin-window kernel.
+struct WindowArgs {
+    const uint32_t *rows;       // token-major index: row t, word w = bins [32w, 32w+32)
+    uint64_t row_words;
+    uint64_t n_bins;
+    const uint32_t *rw;
+    uint64_t nw;
+    const uint64_t *read_off;
+    const uint32_t *read_len;
+    const uint32_t *read_e;
+    uint32_t e_den;
+    uint32_t max_len;
+    const uint64_t *cand_off;   // window sizes
+    const uint32_t *win_lo;     // first bin of each read's window
+    uint64_t n_reads, n_pairs;
+    int32_t *counts;
+    uint32_t *pass_bits;
+    uint32_t *status;
+    uint32_t *counter;
+    int npl;
+};
+
 struct BatchedVariant {
     int q, g, u;
     const void *kernel;
@@ -77,6 +99,9 @@ hipError_t launch_compact(hipStream_t s, const uint32_t *bits, uint64_t n_pairs,
                           uint32_t *surv_bin, uint64_t *n_out, uint64_t *block_sums);
 uint64_t compact_blocks(uint64_t n_pairs);
 hipError_t launch_verify(hipStream_t s, int W, uint32_t grid, const VerifyArgs &a);
+hipError_t launch_transpose(hipStream_t s, int q, const uint32_t *vec, uint64_t n_bins,
+                            uint64_t row_words, uint32_t *rows, uint32_t grid);
+hipError_t launch_window(hipStream_t s, int q, uint32_t grid, size_t lds, const WindowArgs &a);
 hipError_t launch_filter(const void *kernel, dim3 grid, dim3 block, size_t lds_bytes,
                          hipStream_t s, const FilterArgs &a);
 
@@ -90,4 +115,6 @@ struct grim_index {
     void *d_vec;
     uint32_t *d_ref;        // packed reference kept for alignment checks (or null)
     uint64_t ref_words;
+    uint32_t *d_rows;       // token-major copy for the bin-window form (or null)
+    uint64_t row_words;
 };
