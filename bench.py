@@ -93,12 +93,15 @@ def cpu_baseline(w, target_pairs, n_threads):
                 pairs_per_s=n_pairs / dt), (c, p), idx
 
 
-def serving_leg(g, idx, w, rng, loads=(0.25, 0.5, 0.75), seconds=2.5, max_reads=65536):
+def serving_leg(g, idx, w, rng, loads=(0.25, 0.5, 0.75), seconds=2.5, max_reads=65536,
+                inplace=True):
     """Served latency.  Requests of log-uniform size (1..max_reads reads) are cut
     from the workload.  First the server's capacity is measured closed-loop
     (a burst of requests submitted at once); then, for each offered load rho,
     requests arrive as a Poisson process at rho x capacity for `seconds`, and the
-    server's p50/p99 latency (submit -> results in host memory) is recorded."""
+    server's p50/p99 latency (submit -> results in host memory) is recorded.
+    inplace=True submits pinned request buffers without copying (results land in
+    the request's pinned output buffers); False uses the copying submission."""
     n_reads = w["read_len"].size
     reqs = []
     for _ in range(120):
@@ -110,10 +113,11 @@ def serving_leg(g, idx, w, rng, loads=(0.25, 0.5, 0.75), seconds=2.5, max_reads=
         c0, c1 = int(w["cand_off"][r0]), int(w["cand_off"][r1])
         reqs.append(g.HostBatch(w["codes"][o0:o1], w["read_off"][r0:r1] - o0, w["read_len"][r0:r1],
                                 w["read_e"][r0:r1], w["e_den"], w["cand_off"][r0:r1 + 1] - c0,
-                                w["cand_bin"][c0:c1], max_len=250))
+                                w["cand_bin"][c0:c1], max_len=250, pinned=inplace))
     mean_pairs = float(np.mean([hb.n_pairs for hb in reqs]))
     srv = g.Server(idx, hbm_budget_bytes=4 << 30, max_inflight=64, n_streams=3,
                    max_tick_pairs=64 << 20, max_len=256)
+    submit = srv.submit_inplace if inplace else srv.submit
 
     def drain(tickets):
         for t in tickets:
@@ -121,21 +125,23 @@ def serving_leg(g, idx, w, rng, loads=(0.25, 0.5, 0.75), seconds=2.5, max_reads=
             if rc != 0:
                 raise RuntimeError(f"serving request failed: {rc}")
 
-    # closed-loop capacity
+    # warm-up (first use of the buffers and streams), then closed-loop capacity
+    # (each buffer is in flight at most once at a time)
+    drain([submit(hb) for hb in reqs[:60]])
+    srv.stats(reset=True)
     t0 = time.perf_counter()
-    drain([srv.submit(hb) for hb in reqs[:60]])
+    drain([submit(hb) for hb in reqs[:60]])
     cap_wall = time.perf_counter() - t0
     cap_pairs = sum(hb.n_pairs for hb in reqs[:60])
     capacity = cap_pairs / cap_wall
     srv.stats(reset=True)
-    out = dict(requests_per_point=None, mean_pairs_per_request=mean_pairs,
-               capacity_pairs_per_s=capacity, points=[])
+    out = dict(mode="in place, pinned buffers" if inplace else "copying submission",
+               mean_pairs_per_request=mean_pairs, capacity_pairs_per_s=capacity, points=[])
     for rho in loads:
         rate = rho * capacity / mean_pairs          # requests per second
-        n = int(max(20, min(400, rate * seconds)))
+        n = int(max(20, min(len(reqs), rate * seconds)))
         gaps = rng.exponential(1.0 / rate, size=n)
         tickets = []
-        waiter_tickets = []
         t_start = time.perf_counter()
         t_next = t_start
         for i in range(n):
@@ -143,7 +149,7 @@ def serving_leg(g, idx, w, rng, loads=(0.25, 0.5, 0.75), seconds=2.5, max_reads=
             d = t_next - time.perf_counter()
             if d > 0:
                 time.sleep(d)
-            tickets.append(srv.submit(reqs[i % len(reqs)]))
+            tickets.append(submit(reqs[i]))
         drain(tickets)
         wall = time.perf_counter() - t_start
         st = srv.stats(reset=True)
@@ -441,12 +447,15 @@ def main():
     if not args.no_serve:
         try:
             t0 = time.time()
-            serving = serving_leg(g, idx, w, rng)
-            for pt in serving["points"]:
+            serving = serving_leg(g, idx, w, rng, inplace=True)
+            serving["copying_submission"] = serving_leg(g, idx, w, rng, loads=(0.5,),
+                                                        inplace=False)
+            for pt in serving["points"] + serving["copying_submission"]["points"]:
                 log(f"[bench] serving at {pt['offered_load']:.2f} x capacity "
                     f"({pt['offered_rps']:.0f} req/s): p50 {pt['p50_ms']:.2f} ms "
                     f"p99 {pt['p99_ms']:.2f} ms, {pt['pairs_per_s']:.3e} pairs/s")
-            log(f"[bench] serving capacity {serving['capacity_pairs_per_s']:.3e} pairs/s "
+            log(f"[bench] serving capacity {serving['capacity_pairs_per_s']:.3e} pairs/s in place, "
+                f"{serving['copying_submission']['capacity_pairs_per_s']:.3e} copying "
                 f"({time.time() - t0:.1f}s)")
         except Exception as ex:  # report, keep the throughput line
             serving = dict(error=str(ex))

@@ -369,6 +369,17 @@ int grim_serve_create(const grim_index_t *idx, const grim_serve_cfg_t *cfg, grim
  * GRIM_E_BUDGET (the request alone exceeds the budget), GRIM_E_NOMEM. */
 int grim_serve_submit(grim_server_t *s, const grim_batch_t *b, uint64_t *ticket);
 
+/* Queue a request without copying it: the server reads the caller's host
+ * arrays (b) in place and writes the results straight into counts
+ * (n_pairs int32) and pass_bits (ceil(n_pairs / 32) words), both host memory
+ * owned by the caller.  Every one of these buffers must stay alive and
+ * unchanged until grim_serve_poll / grim_serve_wait reports the request done
+ * (or it is cancelled and reported).  Buffers from hipHostMalloc are moved by
+ * direct DMA; pageable memory works but is staged by the runtime.  Same
+ * validation and errors as grim_serve_submit. */
+int grim_serve_submit_inplace(grim_server_t *s, const grim_batch_t *b, int32_t *counts,
+                              uint32_t *pass_bits, uint64_t *ticket);
+
 /* Non-blocking: GRIM_PENDING while the request runs; otherwise copies the
  * results (host counts[n_pairs], pass_bits[ceil(n_pairs/32)]; either may be
  * NULL), fills *st (may be NULL), forgets the ticket and returns the request's

@@ -150,6 +150,7 @@ _SIGS = {
     "grim_graph_destroy": (None, [_vp]),
     "grim_serve_create": (ctypes.c_int, [_vp, _P(grim_serve_cfg_t), _P(_vp)]),
     "grim_serve_submit": (ctypes.c_int, [_vp, _P(grim_batch_t), _P(_u64)]),
+    "grim_serve_submit_inplace": (ctypes.c_int, [_vp, _P(grim_batch_t), _vp, _vp, _P(_u64)]),
     "grim_serve_poll": (ctypes.c_int, [_vp, _u64, _vp, _vp, _P(grim_req_stats_t)]),
     "grim_serve_wait": (ctypes.c_int, [_vp, _u64, ctypes.c_int64, _vp, _vp,
                                        _P(grim_req_stats_t)]),
@@ -576,20 +577,43 @@ def grim_graph_create(index, batch, counts, pass_bits, workspace, tune=None):
 
 
 # ---------------------------------------------------------------------- serving
+def _pinned_copy(a, dtype):
+    """A copy of `a` in page-locked host memory (a numpy view of a pinned
+    torch tensor, which owns the memory)."""
+    torch = _torch()
+    a = np.ascontiguousarray(a, dtype=dtype)
+    t = torch.empty(max(1, a.nbytes), dtype=torch.uint8, pin_memory=True)
+    v = t.numpy().view(dtype)[:a.size]
+    v[...] = a
+    return v, t
+
+
 class HostBatch:
-    """Host arrays of one request and the grim_batch_t pointing at them."""
+    """Host arrays of one request and the grim_batch_t pointing at them.
+
+    pinned=True keeps the arrays (and the result buffers used by in-place
+    submission) in page-locked memory, so the server moves them by direct DMA."""
 
     def __init__(self, codes, read_off, read_len, read_e, e_den, cand_off, cand_bin, max_len=None,
-                 words=None):
-        self.words = np.ascontiguousarray(words if words is not None else grim_pack_bases(codes),
-                                          dtype=np.uint32)
-        self.read_off = np.ascontiguousarray(read_off, dtype=np.uint64)
-        self.read_len = np.ascontiguousarray(read_len, dtype=np.uint32)
-        self.read_e = np.ascontiguousarray(read_e, dtype=np.uint32)
-        self.cand_off = np.ascontiguousarray(cand_off, dtype=np.uint64)
-        self.cand_bin = np.ascontiguousarray(cand_bin, dtype=np.uint32)
-        if self.cand_bin.size == 0:
-            self.cand_bin = np.zeros(1, dtype=np.uint32)
+                 words=None, pinned=False):
+        self._keep = []
+
+        def arr(a, dtype):
+            if not pinned:
+                return np.ascontiguousarray(a, dtype=dtype)
+            v, t = _pinned_copy(a, dtype)
+            self._keep.append(t)
+            return v
+
+        self.words = arr(words if words is not None else grim_pack_bases(codes), np.uint32)
+        self.read_off = arr(read_off, np.uint64)
+        self.read_len = arr(read_len, np.uint32)
+        self.read_e = arr(read_e, np.uint32)
+        self.cand_off = arr(cand_off, np.uint64)
+        self.cand_bin = arr(cand_bin if len(cand_bin) else np.zeros(1, np.uint32), np.uint32)
+        n_out = int(np.asarray(cand_off)[-1]) if len(cand_off) else 0
+        self.out_counts = arr(np.zeros(max(1, n_out), np.int32), np.int32)
+        self.out_bits = arr(np.zeros(max(1, (n_out + 31) // 32), np.uint32), np.uint32)
         self.n_reads = int(self.read_len.size)
         self.n_pairs = int(self.cand_off[-1]) if self.cand_off.size else 0
         self.max_len = int(max_len if max_len is not None else
@@ -621,10 +645,26 @@ class Server:
         self._pending[int(t.value)] = hb.n_pairs
         return int(t.value)
 
+    def submit_inplace(self, hb):
+        """Queue hb without copying; results land in hb.out_counts / hb.out_bits."""
+        t = _u64()
+        rc = _lib.grim_serve_submit_inplace(self._h, ctypes.byref(hb.c),
+                                            hb.out_counts.ctypes.data_as(_vp),
+                                            hb.out_bits.ctypes.data_as(_vp), ctypes.byref(t))
+        if rc != GRIM_OK:
+            raise GrimError(rc, "grim_serve_submit_inplace")
+        self._pending[int(t.value)] = (hb.n_pairs, hb)
+        return int(t.value)
+
     def _result(self, fn, ticket, *extra):
-        n = self._pending.get(ticket, 0)
-        counts = np.empty(max(1, n), dtype=np.int32)
-        bits = np.empty(max(1, (n + 31) // 32), dtype=np.uint32)
+        pend = self._pending.get(ticket, 0)
+        if isinstance(pend, tuple):  # in place: results are already in the batch's buffers
+            n, hb = pend
+            counts, bits = hb.out_counts, hb.out_bits
+        else:
+            n = pend
+            counts = np.empty(max(1, n), dtype=np.int32)
+            bits = np.empty(max(1, (n + 31) // 32), dtype=np.uint32)
         st = grim_req_stats_t()
         rc = fn(self._h, int(ticket), *extra, counts.ctypes.data_as(_vp),
                 bits.ctypes.data_as(_vp), ctypes.byref(st))

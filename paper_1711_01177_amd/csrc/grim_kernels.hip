@@ -25,10 +25,11 @@ namespace grim {
 
 // ------------------------------------------------------------ device helpers
 // Orders the LDS traffic of one wavefront across phases (build planes, read
-// planes, reuse).  Waves of a workgroup never share LDS regions here.
+// planes, reuse).  Waves of a workgroup never share LDS regions in these
+// kernels, so wavefront scope is enough and no memory counters are drained.
 __device__ __forceinline__ void wave_fence()
 {
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
 }
 
@@ -246,6 +247,19 @@ __global__ __launch_bounds__(256) void filter_batched_kernel(FilterArgs a)
                 continue;
             }
             const uint32_t ntok = L >= (uint32_t)Q ? L - Q + 1 : 0u;
+            // bin ids of the segment's first step are requested before the
+            // planes are built, and every step requests the next step's ids
+            // before gathering its own vectors
+            constexpr int STEP = NG * U;
+            auto load_ids = [&](uint64_t c) -> uint32_t {
+                if constexpr (STEP <= kWave) {
+                    const uint64_t kk = c + lane;
+                    return (lane < STEP && kk < pe) ? a.cand_bin[kk] : 0u;
+                } else {
+                    return 0u;
+                }
+            };
+            uint32_t next_ids = load_ids(p);
             const int np = build_planes<Q>(planes, npl, a.rw, a.nw, off, ntok, lane);
             const uint32_t e_num = uniform_u32(a.read_e[r]);
             const uint64_t E = ((uint64_t)e_num * L + a.e_den - 1) / a.e_den;
@@ -261,12 +275,12 @@ __global__ __launch_bounds__(256) void filter_batched_kernel(FilterArgs a)
                                : make_uint4(0, 0, 0, 0);
             }
 
-            for (uint64_t c0 = p; c0 < pe; c0 += (uint64_t)NG * U) {
+            for (uint64_t c0 = p; c0 < pe; c0 += (uint64_t)STEP) {
                 uint32_t bin[U];
                 bool ok[U], inr[U];
-                if constexpr (NG * U <= kWave) {
-                    const uint64_t kk = c0 + lane;
-                    const uint32_t mine = (lane < NG * U && kk < pe) ? a.cand_bin[kk] : 0u;
+                if constexpr (STEP <= kWave) {
+                    const uint32_t mine = next_ids;
+                    next_ids = load_ids(c0 + STEP);
 #pragma unroll
                     for (int u = 0; u < U; ++u)
                         bin[u] = __shfl(mine, u * NG + g);

@@ -155,8 +155,9 @@ ReqLayout req_layout(uint64_t n_words, uint64_t n_reads, uint64_t n_pairs)
 
 struct Request {
     uint64_t ticket = 0;
-    uint8_t *host = nullptr;       // block with inputs and results
+    uint8_t *host = nullptr;       // block with inputs and results (null when in place)
     bool pinned = false;           // block lives in the server's pinned arena
+    bool in_place = false;         // caller-owned arrays used directly
     uint64_t arena_off = 0;
     ReqLayout lay{};
     uint64_t n_words = 0, n_reads = 0, n_pairs = 0;
@@ -167,15 +168,33 @@ struct Request {
     uint32_t flags = 0;
     uint64_t tick = 0;
     Clock::time_point t_submit, t_admit, t_done;
+    // views of the inputs and the result area
+    const uint32_t *p_words = nullptr;
+    const uint64_t *p_read_off = nullptr, *p_cand_off = nullptr;
+    const uint32_t *p_read_len = nullptr, *p_read_e = nullptr, *p_cand_bin = nullptr;
+    int32_t *p_counts = nullptr;
+    uint32_t *p_bits = nullptr;
+    uint64_t zero_off = 0;         // cand_off of a request without reads
 
-    uint32_t *words() const { return reinterpret_cast<uint32_t *>(host + lay.words); }
-    uint64_t *read_off() const { return reinterpret_cast<uint64_t *>(host + lay.read_off); }
-    uint32_t *read_len() const { return reinterpret_cast<uint32_t *>(host + lay.read_len); }
-    uint32_t *read_e() const { return reinterpret_cast<uint32_t *>(host + lay.read_e); }
-    uint64_t *cand_off() const { return reinterpret_cast<uint64_t *>(host + lay.cand_off); }
-    uint32_t *cand_bin() const { return reinterpret_cast<uint32_t *>(host + lay.cand_bin); }
-    int32_t *counts() const { return reinterpret_cast<int32_t *>(host + lay.counts); }
-    uint32_t *bits() const { return reinterpret_cast<uint32_t *>(host + lay.bits); }
+    const uint32_t *words() const { return p_words; }
+    const uint64_t *read_off() const { return p_read_off; }
+    const uint32_t *read_len() const { return p_read_len; }
+    const uint32_t *read_e() const { return p_read_e; }
+    const uint64_t *cand_off() const { return p_cand_off ? p_cand_off : &zero_off; }
+    const uint32_t *cand_bin() const { return p_cand_bin; }
+    int32_t *counts() const { return p_counts; }
+    uint32_t *bits() const { return p_bits; }
+    void view_block()
+    {
+        p_words = reinterpret_cast<const uint32_t *>(host + lay.words);
+        p_read_off = reinterpret_cast<const uint64_t *>(host + lay.read_off);
+        p_read_len = reinterpret_cast<const uint32_t *>(host + lay.read_len);
+        p_read_e = reinterpret_cast<const uint32_t *>(host + lay.read_e);
+        p_cand_off = reinterpret_cast<const uint64_t *>(host + lay.cand_off);
+        p_cand_bin = reinterpret_cast<const uint32_t *>(host + lay.cand_bin);
+        p_counts = reinterpret_cast<int32_t *>(host + lay.counts);
+        p_bits = reinterpret_cast<uint32_t *>(host + lay.bits);
+    }
 };
 
 // Byte layout of one fused tick on the device (and in the staging buffer).
@@ -679,10 +698,13 @@ extern "C" int grim_serve_create(const grim_index_t *idx, const grim_serve_cfg_t
     return GRIM_OK;
 }
 
-extern "C" int grim_serve_submit(grim_server_t *s, const grim_batch_t *b, uint64_t *ticket)
+namespace {
+
+// Checks a host batch the way a solo grim_filter_batch run would need it to be
+// well formed; a malformed request never reaches the device.
+int validate_request(const grim_server_t *s, const grim_batch_t *b)
 {
-    const auto t0 = Clock::now();
-    if (!s || !b || !ticket || b->e_den == 0)
+    if (!s || !b || b->e_den == 0)
         return GRIM_E_INVALID;
     if (b->max_len > s->cfg.max_len)
         return GRIM_E_UNSUPPORTED;
@@ -690,12 +712,10 @@ extern "C" int grim_serve_submit(grim_server_t *s, const grim_batch_t *b, uint64
     if ((n && (!b->read_off || !b->read_len || !b->read_e || !b->cand_off || !b->reads_2bit)) ||
         (P && !b->cand_bin) || (!n && P))
         return GRIM_E_INVALID;
-    // validate on the host: a malformed request never reaches the device
-    const uint64_t nwords = n ? b->n_read_words : 0;
     if (n) {
         if (b->cand_off[0] != 0 || b->cand_off[n] != P)
             return GRIM_E_INVALID;
-        const uint64_t nbases = nwords * 16;
+        const uint64_t nbases = b->n_read_words * 16;
         for (uint64_t i = 0; i < n; ++i) {
             if (b->cand_off[i + 1] < b->cand_off[i])
                 return GRIM_E_INVALID;
@@ -704,39 +724,14 @@ extern "C" int grim_serve_submit(grim_server_t *s, const grim_batch_t *b, uint64
                 return GRIM_E_READ;
         }
     }
+    const uint64_t nwords = n ? b->n_read_words : 0;
     if (plan(nwords + 1, n, P, ws_need(s->idx, P)).total > s->cfg.hbm_budget_bytes)
         return GRIM_E_BUDGET;
-    auto r = std::make_shared<Request>();
-    r->lay = req_layout(nwords, n, P);
-    {
-        std::lock_guard<std::mutex> lk(s->arena_mu);
-        uint64_t off = 0;
-        if (s->arena && s->arena_pool->alloc(r->lay.total, &off)) {
-            r->host = s->arena + off;
-            r->arena_off = off;
-            r->pinned = true;
-        }
-    }
-    if (!r->host) {
-        r->host = static_cast<uint8_t *>(std::aligned_alloc(256, r->lay.total));
-        if (!r->host)
-            return GRIM_E_NOMEM;
-    }
-    par_memcpy(r->words(), b->reads_2bit, nwords * 4);
-    if (n) {
-        std::memcpy(r->read_off(), b->read_off, n * 8);
-        std::memcpy(r->read_len(), b->read_len, n * 4);
-        std::memcpy(r->read_e(), b->read_e, n * 4);
-        std::memcpy(r->cand_off(), b->cand_off, (n + 1) * 8);
-    } else {
-        r->cand_off()[0] = 0;
-    }
-    par_memcpy(r->cand_bin(), b->cand_bin, P * 4);
-    r->e_den = b->e_den;
-    r->n_words = nwords;
-    r->n_reads = n;
-    r->n_pairs = P;
-    r->t_submit = t0;
+    return GRIM_OK;
+}
+
+int enqueue_request(grim_server_t *s, std::shared_ptr<Request> r, uint64_t *ticket)
+{
     {
         std::lock_guard<std::mutex> lk(s->mu);
         if (s->stop) {
@@ -753,6 +748,84 @@ extern "C" int grim_serve_submit(grim_server_t *s, const grim_batch_t *b, uint64
     return GRIM_OK;
 }
 
+}  // namespace
+
+extern "C" int grim_serve_submit(grim_server_t *s, const grim_batch_t *b, uint64_t *ticket)
+{
+    const auto t0 = Clock::now();
+    if (!ticket)
+        return GRIM_E_INVALID;
+    int rc = validate_request(s, b);
+    if (rc)
+        return rc;
+    const uint64_t n = b->n_reads, P = b->n_pairs;
+    const uint64_t nwords = n ? b->n_read_words : 0;
+    auto r = std::make_shared<Request>();
+    r->lay = req_layout(nwords, n, P);
+    {
+        std::lock_guard<std::mutex> lk(s->arena_mu);
+        uint64_t off = 0;
+        if (s->arena && s->arena_pool->alloc(r->lay.total, &off)) {
+            r->host = s->arena + off;
+            r->arena_off = off;
+            r->pinned = true;
+        }
+    }
+    if (!r->host) {
+        r->host = static_cast<uint8_t *>(std::aligned_alloc(256, r->lay.total));
+        if (!r->host)
+            return GRIM_E_NOMEM;
+    }
+    r->view_block();
+    uint8_t *h = r->host;
+    par_memcpy(h + r->lay.words, b->reads_2bit, nwords * 4);
+    if (n) {
+        std::memcpy(h + r->lay.read_off, b->read_off, n * 8);
+        std::memcpy(h + r->lay.read_len, b->read_len, n * 4);
+        std::memcpy(h + r->lay.read_e, b->read_e, n * 4);
+        std::memcpy(h + r->lay.cand_off, b->cand_off, (n + 1) * 8);
+    } else {
+        *reinterpret_cast<uint64_t *>(h + r->lay.cand_off) = 0;
+    }
+    par_memcpy(h + r->lay.cand_bin, b->cand_bin, P * 4);
+    r->e_den = b->e_den;
+    r->n_words = nwords;
+    r->n_reads = n;
+    r->n_pairs = P;
+    r->t_submit = t0;
+    return enqueue_request(s, r, ticket);
+}
+
+extern "C" int grim_serve_submit_inplace(grim_server_t *s, const grim_batch_t *b, int32_t *counts,
+                                         uint32_t *pass_bits, uint64_t *ticket)
+{
+    const auto t0 = Clock::now();
+    if (!ticket)
+        return GRIM_E_INVALID;
+    int rc = validate_request(s, b);
+    if (rc)
+        return rc;
+    const uint64_t n = b->n_reads, P = b->n_pairs;
+    if (P && (!counts || !pass_bits))
+        return GRIM_E_INVALID;
+    auto r = std::make_shared<Request>();
+    r->in_place = true;
+    r->p_words = b->reads_2bit;
+    r->p_read_off = b->read_off;
+    r->p_read_len = b->read_len;
+    r->p_read_e = b->read_e;
+    r->p_cand_off = n ? b->cand_off : nullptr;
+    r->p_cand_bin = b->cand_bin;
+    r->p_counts = counts;
+    r->p_bits = pass_bits;
+    r->e_den = b->e_den;
+    r->n_words = n ? b->n_read_words : 0;
+    r->n_reads = n;
+    r->n_pairs = P;
+    r->t_submit = t0;
+    return enqueue_request(s, r, ticket);
+}
+
 // Hand a finished request's results to the caller.  Called with the server
 // lock held; releases it before copying so the scheduler is not stalled.
 static int finish(grim_server_t *s, std::unique_lock<std::mutex> &lk,
@@ -763,10 +836,10 @@ static int finish(grim_server_t *s, std::unique_lock<std::mutex> &lk,
     Request &r = *rp;
     s->all.erase(it);
     lk.unlock();
-    if ((r.status == GRIM_OK || r.status == GRIM_E_BIN_RANGE) && r.host) {
-        if (counts)
+    if ((r.status == GRIM_OK || r.status == GRIM_E_BIN_RANGE) && r.counts()) {
+        if (counts && counts != r.counts())
             par_memcpy(counts, r.counts(), r.n_pairs * 4);
-        if (pass_bits)
+        if (pass_bits && pass_bits != r.bits())
             std::memcpy(pass_bits, r.bits(), ((r.n_pairs + 31) / 32) * 4);
     }
     if (st) {

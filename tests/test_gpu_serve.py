@@ -202,3 +202,28 @@ def test_mixed_tolerance_denominators(setup):
         rc2, c2, b2 = alone(g, idx, sub)
         assert rc == 0 and np.array_equal(c, c2) and np.array_equal(b, b2)
     srv.destroy()
+
+
+def test_inplace_submission_matches_alone(setup):
+    """Zero-copy submission from pinned buffers: same results as solo runs,
+    mixed with copying submissions in the same server."""
+    g, w, idx = setup
+    reqs = make_requests(g, w, 30, 16, max_reads=800)
+    pinned = []
+    for sub, _ in reqs:
+        pinned.append(g.HostBatch(sub["codes"], sub["read_off"], sub["read_len"], sub["read_e"],
+                                  sub["e_den"], sub["cand_off"], sub["cand_bin"], max_len=256,
+                                  pinned=True))
+    srv = g.Server(idx, hbm_budget_bytes=128 << 20, max_inflight=16, n_streams=3, max_len=256)
+    tickets = []
+    for i, ((sub, hb), phb) in enumerate(zip(reqs, pinned)):
+        tickets.append(srv.submit_inplace(phb) if i % 3 else srv.submit(hb))
+    for i, t in enumerate(tickets):
+        rc, c, b, st = srv.wait(t)
+        assert rc == 0
+        rc2, c2, b2 = alone(g, idx, reqs[i][0])
+        assert np.array_equal(c, c2), i
+        assert np.array_equal(b, b2), i
+        if i % 3:
+            assert np.array_equal(pinned[i].out_counts[:c2.size], c2)
+    srv.destroy()
