@@ -807,7 +807,9 @@ extern "C" int grim_index_transpose(grim_index_t *idx, void *stream)
     const uint64_t row_words = ((idx->n_bins + 63) / 64) * 2;
     const uint64_t n_rows = 1ull << (2 * idx->q);
     uint32_t *rows = nullptr;
-    if (hipMalloc(&rows, n_rows * row_words * 4) != hipSuccess)
+    // one pad word past the last row: the window kernel reads two adjacent
+    // words of a row with one load
+    if (hipMalloc(&rows, n_rows * row_words * 4 + 256) != hipSuccess)
         return GRIM_E_NOMEM;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const uint64_t groups = (idx->n_bins + 63) / 64;
@@ -860,6 +862,7 @@ extern "C" int grim_filter_windows(const grim_index_t *idx, const grim_batch_t *
     std::memset(&a, 0, sizeof(a));
     a.rows = idx->d_rows;
     a.row_words = idx->row_words;
+    a.rows_bytes = (1ull << (2 * idx->q)) * idx->row_words * 4 + 256;
     a.n_bins = idx->n_bins;
     a.rw = b->reads_2bit;
     a.nw = b->n_read_words;
@@ -883,10 +886,7 @@ extern "C" int grim_filter_windows(const grim_index_t *idx, const grim_batch_t *
         HIP_TRY(launch_zero(s, pass_bits, n_words));
     if (b->n_reads == 0)
         return GRIM_OK;
-    uint64_t grid = (uint64_t)cu_count(idx->device) * 4;
-    if (grid > b->n_reads)
-        grid = b->n_reads;
-    HIP_TRY(launch_window(s, idx->q, (uint32_t)grid, (size_t)b->max_len * 4, a));
+    HIP_TRY(launch_window(s, idx->q, (uint32_t)cu_count(idx->device), (size_t)b->max_len * 4, a));
     return GRIM_OK;
 }
 

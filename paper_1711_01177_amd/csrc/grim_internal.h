@@ -61,6 +61,7 @@ struct VerifyArgs {
 struct WindowArgs {
     const uint32_t *rows;       // token-major index: row t, word w = bins [32w, 32w+32)
     uint64_t row_words;
+    uint64_t rows_bytes;        // readable bytes of the row buffer (rows and pad)
     uint64_t n_bins;
     const uint32_t *rw;
     uint64_t nw;
@@ -101,7 +102,9 @@ uint64_t compact_blocks(uint64_t n_pairs);
 hipError_t launch_verify(hipStream_t s, int W, uint32_t grid, const VerifyArgs &a);
 hipError_t launch_transpose(hipStream_t s, int q, const uint32_t *vec, uint64_t n_bins,
                             uint64_t row_words, uint32_t *rows, uint32_t grid);
-hipError_t launch_window(hipStream_t s, int q, uint32_t grid, size_t lds, const WindowArgs &a);
+// Persistent grid: as many workgroups as fit on the device's cus compute units
+// at once (at most one per read).
+hipError_t launch_window(hipStream_t s, int q, uint32_t cus, size_t lds, const WindowArgs &a);
 hipError_t launch_filter(const void *kernel, dim3 grid, dim3 block, size_t lds_bytes,
                          hipStream_t s, const FilterArgs &a);
 

@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstring>
+#include <type_traits>
 
 #include "grim_internal.h"
 
@@ -62,35 +63,108 @@ __global__ __launch_bounds__(256) void transpose_kernel(const uint32_t *__restri
     }
 }
 
-// One workgroup per read (reads taken from an atomic counter); the window of
-// read r is bins [win_lo[r], win_lo[r] + size) with size = cand_off[r+1] -
-// cand_off[r], and pair cand_off[r] + j is bin win_lo[r] + j.  Each round
-// covers 128 row words (4096 bins); counts go through LDS so that the stores
-// are coalesced, and each wavefront ORs the pass bits of 64 consecutive pairs
-// into at most three mask words.
-template <int NP>
-__device__ __forceinline__ void bitsliced_add(uint32_t (&planes)[NP], int npl, uint32_t carry)
+// Carry-save adder: a + b + c = 2*h + l, bitwise over 32 bin lanes.
+__device__ __forceinline__ void csa(uint32_t &h, uint32_t &l, uint32_t a, uint32_t b, uint32_t c)
 {
-#pragma unroll
-    for (int k = 0; k < NP; ++k) {
-        if (k >= npl || !carry)
-            break;
-        const uint32_t c2 = planes[k] & carry;
-        planes[k] ^= carry;
-        carry = c2;
-    }
+    const uint32_t u = a ^ b;
+    h = (u & c) | (~u & a);
+    l = u ^ c;
 }
 
-// NP: bit planes held per thread (8 covers reads of up to 2^8 + q - 2 bases).
-// UN: row loads in flight per thread.
-template <int Q, int NP, int UN>
+// Bit-sliced counter of NP planes: for every bin lane i, the count is
+// ones_i + 2 twos_i + 4 fours_i + 8 eights_i + 16 * (hi planes)_i.  Sixteen
+// words at a time go through a carry-save tree (Harley-Seal), so a word costs
+// about three bitwise operations instead of a ripple over all planes.
+template <int NP>
+struct SlicedCount {
+    uint32_t p[NP];  // p[0] ones, p[1] twos, p[2] fours, p[3] eights, p[4..] weight 16+
+
+    __device__ __forceinline__ void clear()
+    {
+#pragma unroll
+        for (int k = 0; k < NP; ++k)
+            p[k] = 0u;
+    }
+    // add one word at weight 2^k0 (ripple, branch-free)
+    __device__ __forceinline__ void add(uint32_t carry, int k0 = 0)
+    {
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+            if (k >= k0) {
+                const uint32_t c2 = p[k] & carry;
+                p[k] ^= carry;
+                carry = c2;
+            }
+        }
+    }
+    __device__ __forceinline__ void add16(const uint32_t (&w)[16])
+    {
+        uint32_t ta, tb, fa, fb, ea, eb, s16;
+        csa(ta, p[0], p[0], w[0], w[1]);
+        csa(tb, p[0], p[0], w[2], w[3]);
+        csa(fa, p[1], p[1], ta, tb);
+        csa(ta, p[0], p[0], w[4], w[5]);
+        csa(tb, p[0], p[0], w[6], w[7]);
+        csa(fb, p[1], p[1], ta, tb);
+        csa(ea, p[2], p[2], fa, fb);
+        csa(ta, p[0], p[0], w[8], w[9]);
+        csa(tb, p[0], p[0], w[10], w[11]);
+        csa(fa, p[1], p[1], ta, tb);
+        csa(ta, p[0], p[0], w[12], w[13]);
+        csa(tb, p[0], p[0], w[14], w[15]);
+        csa(fb, p[1], p[1], ta, tb);
+        csa(eb, p[2], p[2], fa, fb);
+        csa(s16, p[3], p[3], ea, eb);
+        add(s16, 4);
+    }
+};
+
+// Bins lo + 32j + i (i = 0..31) of token row `row` for virtual column j: the
+// row words holding them, joined by a funnel shift.  The row buffer carries one
+// pad word past its last row, so the second word is always readable; bits taken
+// from beyond a row's end belong to bins >= n_bins, which the caller masks.
+typedef uint32_t u32x2_a4 __attribute__((ext_vector_type(2), aligned(4)));
+
+__device__ __forceinline__ uint32_t row_bins(const char *__restrict__ row, uint32_t byte_off,
+                                            uint32_t sh)
+{
+    const u32x2_a4 v = *reinterpret_cast<const u32x2_a4 *>(row + byte_off);
+    return __builtin_amdgcn_alignbit(v.y, v.x, sh);
+}
+
+// The same through a buffer resource over the whole row buffer, when its size
+// fits 32-bit byte offsets: the row's offset comes from LDS and costs one add.
+__device__ __forceinline__ uint32_t row_bins(__amdgpu_buffer_rsrc_t rs, uint32_t byte_off,
+                                            uint32_t sh)
+{
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, byte_off, 0, 0);
+    return __builtin_amdgcn_alignbit(v[1], v[0], sh);
+}
+
+// One workgroup per read (reads taken from an atomic counter); the window of
+// read r is bins [win_lo[r], win_lo[r] + size) with size = cand_off[r+1] -
+// cand_off[r], and pair cand_off[r] + j is bin win_lo[r] + j.  Column j of a
+// round (128 columns, 4096 bins) owns bins lo + 32(round*128 + j) + [0, 32);
+// the two halves of the block take the first and the second half of the
+// read's token positions, every position adding its token's row bits into the
+// column's bit-sliced counter.  The halves are then added with a bit-sliced
+// ripple adder, pass bits come from a bit-sliced comparison with T, and the
+// counts are unpacked into LDS so that their stores are coalesced.
+// NP: bit planes per counter (8 covers reads of up to 2^8 + q - 2 bases, else 16).
+// OFF32: the row buffer is below 4 GiB; LDS then holds each token's row byte
+// offset instead of the token.
+template <int Q, int NP, bool OFF32>
 __global__ __launch_bounds__(256) void window_kernel(WindowArgs a)
 {
-    extern __shared__ uint32_t toks[];     // the read's tokens (max_len entries)
-    __shared__ int32_t stage[128 * 33];    // counts of the round, padded rows
-    __shared__ uint32_t partial[NP * 128]; // planes of the odd-token half
+    typedef typename std::conditional<NP == 8, uint8_t, uint16_t>::type cnt_t;
+    constexpr int CPW = 4 / sizeof(cnt_t);          // counts per LDS word
+    constexpr int SW = 32 / CPW + 1;                // LDS words per column (padded)
+    extern __shared__ uint32_t toks[];              // the read's tokens (max_len entries)
+    __shared__ uint32_t stage[128 * SW];            // counts of the round
+    __shared__ uint32_t partial[NP * 128];          // counter of the second half
+    __shared__ uint32_t pmask[128];                 // pass bits per column
     __shared__ uint32_t next_read;
-    const int t = threadIdx.x, lane = t & 63, col = t & 127, half = t >> 7;
+    const int t = threadIdx.x, col = t & 127, half = t >> 7;
     for (;;) {
         if (t == 0)
             next_read = atomicAdd(a.counter, 1u);
@@ -119,105 +193,163 @@ __global__ __launch_bounds__(256) void window_kernel(WindowArgs a)
             continue;
         }
         const uint32_t ntok = L >= (uint32_t)Q ? L - Q + 1 : 0u;
-        for (uint32_t i = t; i < ntok; i += blockDim.x)
-            toks[i] = win_token_at<Q>(a.rw, a.nw, off + i);
+        const uint64_t row_bytes = a.row_words * 4;
+        for (uint32_t i = t; i < ntok; i += blockDim.x) {
+            const uint32_t tk = win_token_at<Q>(a.rw, a.nw, off + i);
+            toks[i] = OFF32 ? tk * (uint32_t)row_bytes : tk;
+        }
         __syncthreads();
         const uint64_t E = ((uint64_t)a.read_e[r] * L + a.e_den - 1) / a.e_den;
         const int64_t T = (int64_t)ntok - (int64_t)Q * (int64_t)E;
-        const uint64_t w_first = lo >> 5, w_last = (lo + size - 1) >> 5;
-        // each round: 128 row words (4096 bins); the two halves of the block
-        // take the even and the odd token positions, 8 row loads in flight
-        for (uint64_t wb = w_first; wb <= w_last; wb += 128) {
-            const uint64_t wi = wb + col;
-            uint32_t planes[NP];
+        // first half: tokens [0, hsplit), second: [hsplit, ntok); hsplit is a
+        // multiple of 16 so that both halves start on 16-token blocks
+        const uint32_t hsplit = ((ntok / 2 + 15) / 16) * 16 < ntok ? ((ntok / 2 + 15) / 16) * 16 : ntok;
+        const uint32_t i0 = half ? hsplit : 0u, i1 = half ? ntok : hsplit;
+        const uint64_t wv0 = lo >> 5;
+        const uint32_t sh = (uint32_t)(lo & 31);
+        const uint64_t n_cols = (size + 31) >> 5;
+        const char *rows = reinterpret_cast<const char *>(a.rows);
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<uint32_t *>(a.rows), (short)0, (int)(uint32_t)a.rows_bytes, 0x00020000);
+        for (uint64_t vb = 0; vb < n_cols; vb += 128) {
+            const uint64_t j = vb + col;
+            const uint64_t wi = wv0 + j;
+            SlicedCount<NP> c;
+            c.clear();
+            if (j < n_cols && wi < a.row_words) {
+                const uint32_t bo = (uint32_t)(wi * 4);
+                uint32_t i = i0;
+                for (; i + 16 <= i1; i += 16) {
+                    uint32_t w[16];
 #pragma unroll
-            for (int k = 0; k < NP; ++k)
-                planes[k] = 0u;
-            if (wi <= w_last && wi < a.row_words) {
-                const uint32_t *cp = a.rows + wi;
-                const uint64_t rw = a.row_words;
-                uint32_t i = half;
-                for (; i + 2 * (UN - 1) < ntok; i += 2 * UN) {
-                    uint32_t x[UN];
-#pragma unroll
-                    for (int u = 0; u < UN; ++u)
-                        x[u] = cp[(uint64_t)toks[i + 2 * u] * rw];
-#pragma unroll
-                    for (int u = 0; u < UN; ++u)
-                        bitsliced_add(planes, a.npl, x[u]);
+                    for (int u = 0; u < 16; ++u) {
+                        if (OFF32)
+                            w[u] = row_bins(rs, toks[i + u] + bo, sh);
+                        else
+                            w[u] = row_bins(rows + (uint64_t)toks[i + u] * row_bytes, bo, sh);
+                    }
+                    c.add16(w);
                 }
-                for (; i < ntok; i += 2)
-                    bitsliced_add(planes, a.npl, cp[(uint64_t)toks[i] * rw]);
+                for (; i < i1; ++i) {
+                    if (OFF32)
+                        c.add(row_bins(rs, toks[i] + bo, sh));
+                    else
+                        c.add(row_bins(rows + (uint64_t)toks[i] * row_bytes, bo, sh));
+                }
             }
             if (half == 1) {
 #pragma unroll
                 for (int k = 0; k < NP; ++k)
-                    if (k < a.npl)
-                        partial[k * 128 + col] = planes[k];
+                    partial[k * 128 + col] = c.p[k];
             }
             __syncthreads();
             if (half == 0) {
-                // ripple-carry addition of the two bit-sliced partial sums
+                // ripple-carry addition of the two halves' counters
                 uint32_t carry = 0;
 #pragma unroll
                 for (int k = 0; k < NP; ++k) {
-                    if (k < a.npl) {
-                        const uint32_t x = planes[k], y = partial[k * 128 + col];
-                        planes[k] = x ^ y ^ carry;
-                        carry = (x & y) | (carry & (x ^ y));
-                    }
+                    const uint32_t x = c.p[k], y = partial[k * 128 + col];
+                    c.p[k] = x ^ y ^ carry;
+                    carry = (x & y) | (carry & (x ^ y));
                 }
-                for (int j = 0; j < 32; ++j) {
-                    uint32_t cnt = 0;
+                // bins of this column inside the window and below n_bins
+                uint32_t valid = 0;
+                if (j < n_cols) {
+                    const uint64_t in_win = size - j * 32;
+                    const uint64_t b0 = lo + j * 32;
+                    const uint64_t in_idx = b0 < a.n_bins ? a.n_bins - b0 : 0;
+                    const uint64_t v = in_win < in_idx ? in_win : in_idx;
+                    valid = v >= 32 ? ~0u : ((1u << v) - 1u);
+                }
+                // count >= T, bit-sliced, from the top plane down
+                uint32_t ge;
+                if (T <= 0) {
+                    ge = ~0u;
+                } else if (T >= (int64_t)1 << NP) {
+                    ge = 0u;
+                } else {
+                    uint32_t gt = 0u, eq = ~0u;
 #pragma unroll
-                    for (int k = 0; k < NP; ++k)
-                        if (k < a.npl)
-                            cnt |= ((planes[k] >> j) & 1u) << k;
-                    stage[col * 33 + j] = (int32_t)cnt;
+                    for (int k = NP - 1; k >= 0; --k) {
+                        if ((T >> k) & 1) {
+                            eq &= c.p[k];
+                        } else {
+                            gt |= eq & c.p[k];
+                            eq &= ~c.p[k];
+                        }
+                    }
+                    ge = gt | eq;
+                }
+                pmask[col] = ge & valid;
+                // unpack: count of bin i = sum_k bit i of plane k << k
+                if (NP == 8) {
+#pragma unroll
+                    for (int d = 0; d < 8; ++d) {
+                        uint32_t acc = 0;
+#pragma unroll
+                        for (int k = 0; k < 8; ++k) {
+                            const uint32_t nib = (c.p[k] >> (4 * d)) & 15u;
+                            acc |= ((nib * 0x00204081u) & 0x01010101u) << k;
+                        }
+                        stage[col * SW + d] = acc;
+                    }
+                } else {
+#pragma unroll
+                    for (int d = 0; d < 16; ++d) {
+                        uint32_t acc = 0;
+#pragma unroll
+                        for (int k = 0; k < NP; ++k) {
+                            const uint32_t two = (c.p[k] >> (2 * d)) & 3u;
+                            acc |= ((two * 0x00008001u) & 0x00010001u) << k;
+                        }
+                        stage[col * SW + d] = acc;
+                    }
                 }
             }
             __syncthreads();
-            const uint64_t bin0 = wb * 32;
-            for (uint32_t e0 = 0; e0 < 128 * 32; e0 += 256) {
-                const uint32_t e = e0 + t;
-                const uint64_t bin = bin0 + e;
-                const bool inwin = bin >= lo && bin < lo + size;
-                bool pass = false;
-                if (inwin) {
-                    const uint64_t k = p0 + (bin - lo);
-                    if (bin >= a.n_bins) {
-                        a.counts[k] = -1;
-                        atomicOr(a.status, GRIM_FLAG_BIN_RANGE);
+            // counts: element e of the round is bin lo + 32 vb + e, pair p0 + 32 vb + e
+            const uint64_t base = vb * 32;
+            const cnt_t *sc = reinterpret_cast<const cnt_t *>(stage);
+            bool oob = false;
+            for (uint32_t e = t; e < 128 * 32; e += 256) {
+                const uint64_t pe = base + e;
+                if (pe < size) {
+                    if (lo + pe >= a.n_bins) {
+                        a.counts[p0 + pe] = -1;
+                        oob = true;
                     } else {
-                        const int32_t c = stage[(e >> 5) * 33 + (e & 31)];
-                        a.counts[k] = c;
-                        pass = (int64_t)c >= T;
+                        a.counts[p0 + pe] = (int32_t)sc[(e >> 5) * (SW * CPW) + (e & 31)];
                     }
-                }
-                uint64_t m = __ballot(pass);
-                if (lane == 0 && m) {
-                    const uint64_t bin_w = bin0 + e0 + (uint32_t)(t & ~63);
-                    uint64_t kb;
-                    if (bin_w < lo) {
-                        m >>= (lo - bin_w);
-                        kb = p0;
-                    } else {
-                        kb = p0 + (bin_w - lo);
-                    }
-                    const uint64_t w0 = kb >> 5;
-                    const uint32_t sh = (uint32_t)(kb & 31);
-                    const uint32_t part0 = (uint32_t)(m << sh);
-                    const uint32_t part1 = (uint32_t)(m >> (32 - sh));
-                    const uint32_t part2 = sh ? (uint32_t)(m >> (64 - sh)) : 0u;
-                    if (part0)
-                        atomicOr(&a.pass_bits[w0], part0);
-                    if (part1)
-                        atomicOr(&a.pass_bits[w0 + 1], part1);
-                    if (part2)
-                        atomicOr(&a.pass_bits[w0 + 2], part2);
                 }
             }
-            __syncthreads();  // stage and partial are rewritten next round
+            if (oob)
+                atomicOr(a.status, GRIM_FLAG_BIN_RANGE);
+            // pass bits: column j's 32 bits start at pair p0 + 32 j; global word
+            // g = (p0 >> 5) + vb + m takes the high part of column m - 1 and
+            // the low part of column m.  Words shared with other reads (the
+            // first and the last of the window) are ORed in, the rest stored.
+            if (t <= 128) {
+                const uint32_t ps = (uint32_t)(p0 & 31);
+                const uint64_t g0 = (p0 >> 5) + vb;
+                const uint64_t g_last = (p1 - 1) >> 5;
+                const uint64_t g = g0 + t;
+                if (g <= g_last) {
+                    const uint32_t lo_part = t < 128 ? pmask[t] << ps : 0u;
+                    const uint32_t hi_part = (t > 0 && ps) ? pmask[t - 1] >> (32 - ps) : 0u;
+                    const uint32_t word = lo_part | hi_part;
+                    const bool first = (g == (p0 >> 5)), last = (g == g_last);
+                    // the word past the round's last column gets only a high part;
+                    // the next round (if any) ORs its own low part in
+                    const bool shared = first || last || t == 128 || (t == 0 && vb > 0);
+                    if (shared) {
+                        if (word)
+                            atomicOr(&a.pass_bits[g], word);
+                    } else {
+                        a.pass_bits[g] = word;
+                    }
+                }
+            }
+            __syncthreads();  // stage, partial and pmask are rewritten next round
         }
         __syncthreads();  // toks reused by the next read
     }
@@ -238,15 +370,18 @@ hipError_t launch_transpose(hipStream_t s, int q, const uint32_t *vec, uint64_t 
     return hipGetLastError();
 }
 
-hipError_t launch_window(hipStream_t s, int q, uint32_t grid, size_t lds, const WindowArgs &a)
+hipError_t launch_window(hipStream_t s, int q, uint32_t cus, size_t lds, const WindowArgs &a)
 {
     WindowArgs copy = a;
     void *args[] = {&copy};
     const void *k = nullptr;
     const bool small = a.npl <= 8;
+    const bool off32 = a.rows_bytes < (1ull << 32);
 #define GRIM_WK(Q)                                                                          \
-    k = small ? reinterpret_cast<const void *>(&window_kernel<Q, 8, 16>)                    \
-              : reinterpret_cast<const void *>(&window_kernel<Q, 16, 8>)
+    k = small ? (off32 ? reinterpret_cast<const void *>(&window_kernel<Q, 8, true>)         \
+                       : reinterpret_cast<const void *>(&window_kernel<Q, 8, false>))       \
+              : (off32 ? reinterpret_cast<const void *>(&window_kernel<Q, 16, true>)        \
+                       : reinterpret_cast<const void *>(&window_kernel<Q, 16, false>))
     switch (q) {
     case 4: GRIM_WK(4); break;
     case 5: GRIM_WK(5); break;
@@ -255,7 +390,14 @@ hipError_t launch_window(hipStream_t s, int q, uint32_t grid, size_t lds, const 
     default: return hipErrorInvalidValue;
     }
 #undef GRIM_WK
-    return hipLaunchKernel(k, dim3(grid), dim3(256), args, lds, s);
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 256, lds);
+    if (e != hipSuccess)
+        return e;
+    uint64_t grid = (uint64_t)cus * (uint64_t)(per_cu > 0 ? per_cu : 1);
+    if (grid > a.n_reads)
+        grid = a.n_reads;
+    return hipLaunchKernel(k, dim3((uint32_t)grid), dim3(256), args, lds, s);
 }
 
 }  // namespace grim

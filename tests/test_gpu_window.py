@@ -91,3 +91,33 @@ def test_transpose_layout():
     out = run_windows(g, idx, w, [0] * 256)
     got = out[0].reshape(256, nb)
     assert np.array_equal(got, bits.T.astype(np.int32))
+
+
+def test_windows_token_blocks_and_many_reads():
+    """Token counts around the 16-token blocks of the counter (ntok 0 ... 70,
+    including reads shorter than q), windows of every alignment and size up
+    to 9,000 bins, and more reads than the persistent grid has workgroups."""
+    g = lib()
+    q, B, O = 5, 150, 110
+    ref = gs.reference(61, 1_200_000, 0.3, 30, 300, 0.85, 0.98)
+    nb = (ref.size + B - 1) // B
+    rng = np.random.default_rng(62)
+    n = 2500
+    ntoks = np.concatenate([np.arange(0, 71), rng.integers(0, 250, size=n - 71)])
+    lens = np.maximum(ntoks + q - 1, 1)
+    lens[:3] = [1, 3, 4]                      # shorter than q: no tokens
+    reads, e_nums = [], []
+    for i, L in enumerate(lens):
+        z = int(rng.integers(0, ref.size - L))
+        reads.append(ref[z:z + L].copy())
+        e_nums.append(int(rng.choice([0, 300, 500, 1000])))
+    sizes = rng.choice([1, 5, 31, 32, 33, 63, 64, 65, 127, 128, 129, 4095, 4096, 4097, 9000],
+                       size=n)
+    win_lo = rng.integers(0, nb, size=n)
+    w = window_workload(ref, q, B, O, reads, e_nums, win_lo, sizes)
+    idx = g.grim_build_bins(ref, q, B, O)
+    idx.transpose()
+    out = run_windows(g, idx, w, win_lo)
+    orc = oracle_run(w)
+    assert out[2] == (g.GRIM_E_BIN_RANGE if orc[2] else 0)
+    assert_same(out, orc, "token blocks")
