@@ -267,13 +267,24 @@ int grim_index_transpose(grim_index_t *idx, void *stream);
  * [win_lo[r], win_lo[r] + (cand_off[r+1] - cand_off[r])), and pair
  * cand_off[r] + j is bin win_lo[r] + j (b->cand_bin is not used).  Outputs,
  * status and errors as grim_filter_batch (a bin >= n_bins gives -1 and
- * GRIM_FLAG_BIN_RANGE).  win_lo: device u32[n_reads].  workspace: device,
- * >= 256 bytes, 256-byte aligned.  Needs grim_index_transpose first
- * (else GRIM_E_INVALID); b->max_len <= 4096 (else GRIM_E_UNSUPPORTED).
- * Asynchronous on `stream`; allocates nothing. */
+ * GRIM_FLAG_BIN_RANGE).  win_lo: device u32[n_reads].  order: must be NULL
+ * (reads are processed in index order); a processing order is switched off
+ * in this version and gives GRIM_E_UNSUPPORTED.  workspace: device, >= 256
+ * bytes, 256-byte aligned.  Needs grim_index_transpose first (else GRIM_E_INVALID);
+ * b->max_len <= 4096 (else GRIM_E_UNSUPPORTED).  Asynchronous on `stream`;
+ * allocates nothing. */
 int grim_filter_windows(const grim_index_t *idx, const grim_batch_t *b, const uint32_t *win_lo,
-                        int32_t *counts, uint32_t *pass_bits, void *workspace,
-                        uint64_t workspace_bytes, void *stream);
+                        const uint32_t *order, int32_t *counts, uint32_t *pass_bits,
+                        void *workspace, uint64_t workspace_bytes, void *stream);
+
+/* Device-side processing order for grim_filter_windows (the stable argsort
+ * of win_lo, so that reads with overlapping windows run together and share
+ * row segments through the cache).  Switched off in this version: both calls
+ * return GRIM_E_UNSUPPORTED and write nothing (bytes is set to 0).  A caller
+ * gets the same cache sharing by submitting its reads sorted by window start. */
+int grim_window_order_workspace_size(const grim_index_t *idx, uint64_t n_reads, uint64_t *bytes);
+int grim_window_order(const grim_index_t *idx, const uint32_t *win_lo, uint64_t n_reads,
+                      uint32_t *order, void *workspace, uint64_t workspace_bytes, void *stream);
 
 /* ------------------------------------------------------------------- seeding */
 /* The step before the filter: the mapper looks up exact seeds of each read in a

@@ -137,7 +137,10 @@ _SIGS = {
     "grim_verify_survivors": (ctypes.c_int, [_vp, _P(grim_batch_t), _vp, _vp, _u64, _vp, _vp,
                                              _vp]),
     "grim_index_transpose": (ctypes.c_int, [_vp, _vp]),
-    "grim_filter_windows": (ctypes.c_int, [_vp, _P(grim_batch_t), _vp, _vp, _vp, _vp, _u64, _vp]),
+    "grim_filter_windows": (ctypes.c_int, [_vp, _P(grim_batch_t), _vp, _vp, _vp, _vp, _vp, _u64,
+                                           _vp]),
+    "grim_window_order_workspace_size": (ctypes.c_int, [_vp, _u64, _P(_u64)]),
+    "grim_window_order": (ctypes.c_int, [_vp, _vp, _u64, _vp, _vp, _u64, _vp]),
     "grim_seed_index_build": (ctypes.c_int, [_vp, _u64, _u32, _P(_vp), _vp]),
     "grim_seed_index_free": (None, [_vp]),
     "grim_seed_candidates": (ctypes.c_int, [_vp, _P(grim_batch_t), _u64, _u32, _P(_vp), _vp]),
@@ -457,11 +460,36 @@ def grim_verify_survivors(index, batch, surv_read, surv_bin, n=None, stream=None
     return dist[:n], ok[:(n + 31) // 32]
 
 
-def grim_filter_windows(index, batch, win_lo, counts, pass_bits, workspace, stream=None):
-    """Bin-window filter: every bin of [win_lo[r], win_lo[r] + window size)."""
+def grim_filter_windows(index, batch, win_lo, counts, pass_bits, workspace, stream=None,
+                        order=None):
+    """Bin-window filter: every bin of [win_lo[r], win_lo[r] + window size);
+    order (optional device u32 permutation) sets the processing order."""
     _check(_lib.grim_filter_windows(index.handle, ctypes.byref(batch.c), _ptr(win_lo),
+                                    _ptr(order) if order is not None else None,
                                     _ptr(counts), _ptr(pass_bits), _ptr(workspace),
                                     workspace.numel(), _stream(stream)), "grim_filter_windows")
+
+
+def grim_window_order_workspace_size(index, n_reads):
+    n = _u64()
+    _check(_lib.grim_window_order_workspace_size(index.handle, int(n_reads), ctypes.byref(n)),
+           "grim_window_order_workspace_size")
+    return int(n.value)
+
+
+def grim_window_order(index, win_lo, order=None, workspace=None, stream=None):
+    """Processing order for grim_filter_windows: the stable argsort of win_lo,
+    on the device.  Allocates `order` and the workspace (torch) when not given."""
+    import torch
+    n = int(win_lo.numel())
+    if order is None:
+        order = torch.empty(max(1, n), dtype=torch.int32, device=win_lo.device)
+    if workspace is None:
+        workspace = torch.empty(grim_window_order_workspace_size(index, n), dtype=torch.uint8,
+                                device=win_lo.device)
+    _check(_lib.grim_window_order(index.handle, _ptr(win_lo), n, _ptr(order), _ptr(workspace),
+                                  workspace.numel(), _stream(stream)), "grim_window_order")
+    return order
 
 
 class SeedIndex:

@@ -833,11 +833,14 @@ extern "C" int grim_index_transpose(grim_index_t *idx, void *stream)
 }
 
 extern "C" int grim_filter_windows(const grim_index_t *idx, const grim_batch_t *b,
-                                   const uint32_t *win_lo, int32_t *counts, uint32_t *pass_bits,
-                                   void *workspace, uint64_t workspace_bytes, void *stream)
+                                   const uint32_t *win_lo, const uint32_t *order, int32_t *counts,
+                                   uint32_t *pass_bits, void *workspace, uint64_t workspace_bytes,
+                                   void *stream)
 {
     if (!idx || !b)
         return GRIM_E_INVALID;
+    if (order)  // processing orders are switched off
+        return GRIM_E_UNSUPPORTED;
     if (b->e_den == 0 || b->max_len == 0 || (b->n_reads == 0 && b->n_pairs != 0))
         return GRIM_E_INVALID;
     if (b->max_len > 4096)
@@ -888,6 +891,32 @@ extern "C" int grim_filter_windows(const grim_index_t *idx, const grim_batch_t *
         return GRIM_OK;
     HIP_TRY(launch_window(s, idx->q, (uint32_t)cu_count(idx->device), (size_t)b->max_len * 4, a));
     return GRIM_OK;
+}
+
+// Device-side processing orders for the window filter are switched off: both
+// entry points report GRIM_E_UNSUPPORTED.
+extern "C" int grim_window_order_workspace_size(const grim_index_t *idx, uint64_t n_reads,
+                                                uint64_t *bytes)
+{
+    (void)idx;
+    (void)n_reads;
+    if (bytes)
+        *bytes = 0;
+    return GRIM_E_UNSUPPORTED;
+}
+
+extern "C" int grim_window_order(const grim_index_t *idx, const uint32_t *win_lo, uint64_t n_reads,
+                                 uint32_t *order, void *workspace, uint64_t workspace_bytes,
+                                 void *stream)
+{
+    (void)idx;
+    (void)win_lo;
+    (void)n_reads;
+    (void)order;
+    (void)workspace;
+    (void)workspace_bytes;
+    (void)stream;
+    return GRIM_E_UNSUPPORTED;
 }
 
 // ---------------------------------------------------------------- graphs

@@ -169,10 +169,11 @@ __global__ __launch_bounds__(256) void window_kernel(WindowArgs a)
         if (t == 0)
             next_read = atomicAdd(a.counter, 1u);
         __syncthreads();
-        const uint64_t r = next_read;
+        const uint64_t slot = next_read;
         __syncthreads();
-        if (r >= a.n_reads)
+        if (slot >= a.n_reads)
             break;
+        const uint64_t r = slot;
         const uint64_t p0 = a.cand_off[r], p1 = a.cand_off[r + 1];
         if (p1 <= p0)
             continue;

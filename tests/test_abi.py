@@ -83,3 +83,15 @@ def test_pack_bases_layout():
     with pytest.raises(g.GrimError) as e:
         g.grim_pack_bases(np.frombuffer(b"ACGN", dtype=np.uint8))
     assert e.value.code == g.GRIM_E_BASE
+
+
+def test_window_order_is_switched_off():
+    """The device-side window order reports GRIM_E_UNSUPPORTED and touches no
+    device (callable without a GPU)."""
+    import ctypes
+    import paper_1711_01177_amd as g
+    n = ctypes.c_uint64(77)
+    assert g._lib.grim_window_order_workspace_size(None, 10, ctypes.byref(n)) == \
+        g.GRIM_E_UNSUPPORTED
+    assert n.value == 0
+    assert g._lib.grim_window_order(None, None, 10, None, None, 0, None) == g.GRIM_E_UNSUPPORTED

@@ -11,7 +11,7 @@ from tests.gpu_helpers import assert_same, custom_workload, gpu_run, lib, oracle
 pytestmark = pytest.mark.gpu
 
 
-def run_windows(g, idx, w, win_lo, max_len=None):
+def run_windows(g, idx, w, win_lo, max_len=None, order=None):
     import torch
     b = g.Batch.from_workload(w, max_len=max_len)
     n = b.n_pairs
@@ -19,7 +19,11 @@ def run_windows(g, idx, w, win_lo, max_len=None):
     counts.fill_(-9)
     ws = torch.zeros(256, dtype=torch.uint8, device="cuda")
     wl = torch.from_numpy(np.ascontiguousarray(win_lo, dtype=np.uint32).view(np.int32)).cuda()
-    g.grim_filter_windows(idx, b, wl, counts, bits, ws)
+    if isinstance(order, str) and order == "sorted":
+        order = g.grim_window_order(idx, wl)
+    elif order is not None:
+        order = torch.from_numpy(np.ascontiguousarray(order, dtype=np.uint32).view(np.int32)).cuda()
+    g.grim_filter_windows(idx, b, wl, counts, bits, ws, order=order)
     rc, flags = g.grim_filter_status(ws)
     torch.cuda.synchronize()
     return (counts.cpu().numpy()[:n].copy(),
@@ -121,3 +125,50 @@ def test_windows_token_blocks_and_many_reads():
     orc = oracle_run(w)
     assert out[2] == (g.GRIM_E_BIN_RANGE if orc[2] else 0)
     assert_same(out, orc, "token blocks")
+
+
+@pytest.mark.skip(reason="device-side window order switched off: its first GPU run stopped "
+                         "responding with no cause found by reading; the entry points return "
+                         "GRIM_E_UNSUPPORTED until one is shown")
+def test_window_order_and_ordered_filter():
+    """grim_window_order is the stable argsort of the window starts; filtering in
+    that order, or in any other permutation, gives the same outputs as index
+    order; an order entry past the last read is skipped and flagged."""
+    import torch
+    g = lib()
+    q, B, O = 5, 200, 105
+    ref = gs.reference(71, 1_000_000, 0.3, 30, 300, 0.85, 0.98)
+    nb = (ref.size + B - 1) // B
+    rng = np.random.default_rng(72)
+    rd = gs.reads(73, ref, 700, [100, 150, 250], [500, 1000])
+    reads = [rd["codes"][int(o):int(o) + int(L)] for o, L in zip(rd["read_off"], rd["read_len"])]
+    n = len(reads)
+    sizes = rng.choice([1, 33, 500, 2048], size=n)
+    win_lo = np.minimum(rd["read_z"] // B, nb - 1).astype(np.int64) - sizes // 2
+    win_lo = np.clip(win_lo, 0, nb - 1)
+    win_lo[:50] = rng.integers(0, 40, size=50)       # many equal and near-equal keys
+    win_lo[50:60] = 7
+    w = window_workload(ref, q, B, O, reads, rd["read_e"], win_lo, sizes)
+    idx = g.grim_build_bins(ref, q, B, O)
+    idx.transpose()
+    wl = torch.from_numpy(win_lo.astype(np.uint32).view(np.int32)).cuda()
+    order = g.grim_window_order(idx, wl)
+    torch.cuda.synchronize()
+    got = order.cpu().numpy().view(np.uint32)[:n]
+    assert np.array_equal(got, np.argsort(win_lo, kind="stable").astype(np.uint32))
+    base = run_windows(g, idx, w, win_lo)
+    orc = oracle_run(w)
+    assert_same(base, orc, "index order")
+    assert_same(run_windows(g, idx, w, win_lo, order="sorted"), orc, "sorted order")
+    assert_same(run_windows(g, idx, w, win_lo, order=rng.permutation(n)), orc, "random order")
+    # one slot names a read that does not exist: that slot is skipped and
+    # flagged, the read it replaced keeps its initial counts, the rest is exact
+    bad = np.arange(n)
+    bad[5] = n + 3
+    c, b, rc, flags = run_windows(g, idx, w, win_lo, order=bad)
+    assert rc == g.GRIM_E_READ
+    p0, p1 = int(w["cand_off"][5]), int(w["cand_off"][6])
+    assert np.all(c[p0:p1] == -9)
+    keep = np.ones(c.size, bool)
+    keep[p0:p1] = False
+    assert np.array_equal(c[keep], orc[0][keep])
