@@ -106,7 +106,7 @@ def cpu_baseline(w, target_pairs, n_threads, idx=None):
 
 
 def serving_leg(g, idx, w, rng, loads=(0.25, 0.5, 0.75, 0.9), n_requests=10_000, pool=256,
-                max_reads=65536, inplace=True):
+                max_reads=65536, inplace=True, tick_pairs=64 << 20, n_streams=3):
     """Served latency.  A pool of `pool` requests of log-uniform size
     (1..max_reads reads) is cut from the workload.  First the server's capacity
     is measured closed-loop (a burst of requests submitted at once); then, for
@@ -115,7 +115,9 @@ def serving_leg(g, idx, w, rng, loads=(0.25, 0.5, 0.75, 0.9), n_requests=10_000,
     flight, and the server's p50/p99 latency (submit -> results in host memory)
     is recorded.  inplace=True submits pinned request buffers without copying
     (results land in the request's pinned output buffers, so a buffer is in
-    flight at most once at a time); False uses the copying submission."""
+    flight at most once at a time); False uses the copying submission.  Ticks
+    hold at most tick_pairs pairs, so larger requests run in parts whose copies
+    and launches overlap on n_streams streams."""
     n_reads = w["read_len"].size
     reqs = []
     for _ in range(pool):
@@ -129,8 +131,8 @@ def serving_leg(g, idx, w, rng, loads=(0.25, 0.5, 0.75, 0.9), n_requests=10_000,
                                 w["read_e"][r0:r1], w["e_den"], w["cand_off"][r0:r1 + 1] - c0,
                                 w["cand_bin"][c0:c1], max_len=250, pinned=inplace))
     mean_pairs = float(np.mean([hb.n_pairs for hb in reqs]))
-    srv = g.Server(idx, hbm_budget_bytes=4 << 30, max_inflight=64, n_streams=3,
-                   max_tick_pairs=64 << 20, max_len=256)
+    srv = g.Server(idx, hbm_budget_bytes=4 << 30, max_inflight=64, n_streams=n_streams,
+                   max_tick_pairs=tick_pairs, max_len=256)
     submit = srv.submit_inplace if inplace else srv.submit
 
     def finish(rc, ticket):
@@ -141,17 +143,22 @@ def serving_leg(g, idx, w, rng, loads=(0.25, 0.5, 0.75, 0.9), n_requests=10_000,
         for t in tickets:
             finish(srv.wait(t)[0], t)
 
-    # warm-up (first use of the buffers and streams), then closed-loop capacity
-    # over the whole pool (each buffer is in flight at most once at a time)
-    drain([submit(hb) for hb in reqs[:pool // 2]])
-    srv.stats(reset=True)
-    t0 = time.perf_counter()
+    # warm-up over the whole pool (first use of every buffer; the server's
+    # staging buffers reach their final size), then closed-loop capacity: the
+    # whole pool submitted at once, twice (each buffer is in flight at most once
+    # at a time), pairs over the mean wall time
     drain([submit(hb) for hb in reqs])
-    cap_wall = time.perf_counter() - t0
-    capacity = sum(hb.n_pairs for hb in reqs) / cap_wall
+    walls = []
+    for _ in range(2):
+        t0 = time.perf_counter()
+        drain([submit(hb) for hb in reqs])
+        walls.append(time.perf_counter() - t0)
+    capacity = sum(hb.n_pairs for hb in reqs) / float(np.mean(walls))
     srv.stats(reset=True)
     out = dict(mode="in place, pinned buffers" if inplace else "copying submission",
                pool_requests=pool, mean_pairs_per_request=mean_pairs,
+               max_tick_pairs=tick_pairs, n_streams=n_streams,
+               capacity_burst_s=walls,
                capacity_pairs_per_s=capacity, points=[])
     for rho in loads:
         rate = rho * capacity / mean_pairs          # requests per second
@@ -580,6 +587,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms,
+        "step_ms_median": float(np.median(step_ms)),
+        "step_ms_min_max": [float(min(step_ms)), float(max(step_ms))],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

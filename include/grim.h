@@ -338,7 +338,10 @@ void grim_graph_destroy(grim_graph_t *g);
  * requests while their device bytes fit in the HBM budget and a slot is free,
  * fuses the admitted requests of one tick into a single batched launch on one
  * of n_streams streams, and keeps admitting new requests while earlier ticks
- * run.  Results are bit-identical to filtering each request alone.  Mirrors the
+ * run.  A request with more pairs than max_tick_pairs is cut at read
+ * boundaries into parts that run as separate ticks, so that its copies and
+ * launches overlap across streams.  Results are bit-identical to filtering
+ * each request alone.  Mirrors the
  * overlap of filtering with the mapper's alignment through a bitmask buffer
  * (Sections "Mapping GRIM-Filter to 3D-Stacked Memory with PIM" and "GRIM-Filter
  * Parallelization"). */
@@ -348,7 +351,8 @@ typedef struct grim_serve_cfg {
     uint64_t hbm_budget_bytes;  /* device bytes for request buffers (0 = 1 GiB)     */
     uint32_t max_inflight;      /* requests on the device at once (0 = 64)          */
     uint32_t n_streams;         /* concurrent ticks (0 = 2)                         */
-    uint32_t max_tick_pairs;    /* pairs fused into one launch (0 = 64M)            */
+    uint32_t max_tick_pairs;    /* pairs per launch; larger requests run in parts
+                                   of whole reads (0 = 64M)                         */
     uint32_t max_len;           /* longest read accepted (0 = 1024)                 */
 } grim_serve_cfg_t;
 
@@ -356,7 +360,8 @@ typedef struct grim_req_stats {
     double queue_ms;       /* submit -> admitted                                    */
     double latency_ms;     /* submit -> results in host memory                      */
     uint64_t n_pairs;
-    uint64_t tick;         /* which fused launch carried the request                */
+    uint64_t tick;         /* the fused launch that carried the request (its last
+                              part, for a request run in parts)                     */
     uint32_t flags;        /* GRIM_FLAG_* bits seen in this request's pairs         */
     int32_t status;        /* GRIM_OK, GRIM_E_BIN_RANGE, GRIM_E_READ, GRIM_E_CANCELLED */
 } grim_req_stats_t;
@@ -404,7 +409,8 @@ int grim_serve_wait(grim_server_t *s, uint64_t ticket, int64_t timeout_ms, int32
                     uint32_t *pass_bits, grim_req_stats_t *st);
 
 /* Cancel a request: a queued request never runs; a running one has its results
- * dropped.  Its poll/wait then returns GRIM_E_CANCELLED. */
+ * dropped (parts not yet admitted never run).  Its poll/wait then returns
+ * GRIM_E_CANCELLED. */
 int grim_serve_cancel(grim_server_t *s, uint64_t ticket);
 
 /* Aggregate statistics since creation (or the last reset). */

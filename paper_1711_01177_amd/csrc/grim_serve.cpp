@@ -7,18 +7,23 @@
 //   (1) retires finished ticks: realigns each request's slice of the fused pass
 //       bits, and marks the requests done;
 //   (2) while a stream slot is free, admits queued requests in arrival order
-//       while their device bytes fit in what is left of the HBM budget, fuses
-//       them into one batch and queues on that slot's stream: H2D copies (large
-//       array slices straight from the request's pinned block, runs of small
-//       slices through the slot's staging buffer, re-based offset arrays always
-//       staged), one batched filter launch, and D2H copies (large count slices
-//       straight into the request's result area).
-// Ticks on different streams overlap on the device, and requests that arrive
-// while ticks run join the next tick as soon as memory and a slot free up.
+//       while their device bytes fit in what is left of the HBM budget and the
+//       tick has fewer than max_tick_pairs pairs, fuses them into one batch and
+//       queues on that slot's stream: H2D copies (large array slices straight
+//       from the request's pinned block, runs of small slices through the
+//       slot's staging buffer, re-based offset arrays always staged), one
+//       batched filter launch, and D2H copies (large count slices straight into
+//       the request's result area).
+// A request with more pairs than a tick has room for is admitted in parts, cut
+// at read boundaries; its parts run as separate ticks on the free streams, so
+// one part's H2D copy overlaps another part's filter and D2H copy, and the
+// request is done when its last part has been retired.  Ticks on different
+// streams overlap on the device, and requests that arrive while ticks run join
+// the next tick as soon as memory and a slot free up.
 //
-// Fusing only concatenates and re-bases offsets, and every pair is computed by
-// the same kernel from the same read and bin, so each request's counts and
-// pass bits are identical to filtering it alone.
+// Fusing and splitting only concatenate, cut and re-base offsets, and every
+// pair is computed by the same kernel from the same read and bin, so each
+// request's counts and pass bits are identical to filtering it alone.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -167,6 +172,9 @@ struct Request {
     int status = GRIM_OK;
     uint32_t flags = 0;
     uint64_t tick = 0;
+    uint64_t next_read = 0;        // first read not yet admitted to a tick
+    bool all_admitted = false;     // every read is in a tick (or the request was dropped)
+    uint32_t parts_open = 0;       // admitted parts whose tick has not been retired
     Clock::time_point t_submit, t_admit, t_done;
     // views of the inputs and the result area
     const uint32_t *p_words = nullptr;
@@ -237,15 +245,22 @@ Layout plan(uint64_t n_words, uint64_t n_reads, uint64_t n_pairs, uint64_t ws_by
     return L;
 }
 
+// One request's reads [ra, rb) (pairs [pa, pb) of the request) inside a tick.
+struct Part {
+    std::shared_ptr<Request> r;
+    uint64_t ra = 0, rb = 0, pa = 0, pb = 0;
+    uint64_t wlo = 0, nw = 0;      // the request's packed words the part's reads use
+    uint64_t fused_base = 0;       // first pair of the part in the fused tick
+    bool counts_direct = false;    // counts came back by direct DMA
+};
+
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
     uint8_t *stage = nullptr;      // pinned staging buffer, mirrors the tick layout
     uint64_t stage_bytes = 0;
     bool busy = false;
-    std::vector<std::shared_ptr<Request>> reqs;
-    std::vector<uint64_t> pair_base;
-    std::vector<char> counts_direct;  // per request: counts came back by direct DMA
+    std::vector<Part> parts;
     Layout lay;
     uint64_t dev_off = 0;
     uint64_t tick = 0;
@@ -285,6 +300,8 @@ struct grim_server {
     void run();
     bool launch_tick(std::unique_lock<std::mutex> &lk);
     void retire(Slot &s);
+    void part_closed(Request &r, Clock::time_point now);
+    void drop_from_queue(const Request &r);
     void free_block(Request &r);
 };
 
@@ -312,6 +329,67 @@ void grim_server::free_block(Request &r)
     r.host = nullptr;
 }
 
+namespace {
+
+// OR n bits of src starting at bit sb into dst starting at bit db (dst words
+// outside [db, db + n) keep their other bits).  src must be readable one word
+// past its last used bit.
+void or_bits(uint32_t *dst, uint64_t db, const uint32_t *src, uint64_t sb, uint64_t n)
+{
+    uint64_t done = 0;
+    while (done < n) {
+        const uint64_t d = db + done, sp = sb + done;
+        const uint32_t dsh = (uint32_t)(d & 31);
+        const uint64_t take = std::min<uint64_t>(32 - dsh, n - done);
+        const uint32_t ssh = (uint32_t)(sp & 31);
+        uint32_t x = src[sp >> 5] >> ssh;
+        if (ssh && ssh + take > 32)
+            x |= src[(sp >> 5) + 1] << (32 - ssh);
+        if (take < 32)
+            x &= (1u << take) - 1u;
+        dst[d >> 5] |= x << dsh;
+        done += take;
+    }
+}
+
+}  // namespace
+
+// A part of r has been retired (or dropped): finish r once nothing of it is
+// left in flight and no read waits for admission.  Called with mu held.
+void grim_server::part_closed(Request &r, Clock::time_point now)
+{
+    if (r.parts_open)
+        --r.parts_open;
+    if (r.parts_open || !r.all_admitted || r.state == State::Done)
+        return;
+    if (r.cancelled) {
+        r.status = GRIM_E_CANCELLED;
+        ++cancelled;
+    } else if (r.status != GRIM_OK && r.status != GRIM_E_BIN_RANGE) {
+        ++failed;
+    } else {
+        const bool bad = (r.flags & GRIM_FLAG_BIN_RANGE) != 0;
+        r.status = bad ? GRIM_E_BIN_RANGE : GRIM_OK;
+        if (bad)
+            ++failed;
+        ++completed;
+        pairs_done += r.n_pairs;
+        lat.push_back(ms_between(r.t_submit, now));
+    }
+    r.t_done = now;
+    r.state = State::Done;
+    --inflight_reqs;
+}
+
+void grim_server::drop_from_queue(const Request &r)
+{
+    for (auto q = queue.begin(); q != queue.end(); ++q)
+        if (q->get() == &r) {
+            queue.erase(q);
+            return;
+        }
+}
+
 void grim_server::retire(Slot &s)
 {
     // called with mu held, after s.done completed
@@ -320,49 +398,26 @@ void grim_server::retire(Slot &s)
     const uint32_t *bits = reinterpret_cast<const uint32_t *>(out + s.lay.bits);
     const uint32_t status = *reinterpret_cast<const uint32_t *>(out + s.lay.status);
     const auto now = Clock::now();
-    for (size_t j = 0; j < s.reqs.size(); ++j) {
-        Request &r = *s.reqs[j];
-        const uint64_t base = s.pair_base[j];
-        if (!r.cancelled) {
-            if (!s.counts_direct[j] && r.n_pairs)
-                std::memcpy(r.counts(), counts + base, r.n_pairs * 4);
-            const uint64_t nw = (r.n_pairs + 31) / 32;
-            uint32_t *rb = r.bits();
-            const uint64_t w0 = base >> 5;
-            const uint32_t sh = (uint32_t)(base & 31);
-            for (uint64_t w = 0; w < nw; ++w) {
-                uint32_t x = bits[w0 + w] >> sh;
-                if (sh && (w0 + w + 1) * 32 < base + r.n_pairs)
-                    x |= bits[w0 + w + 1] << (32 - sh);
-                rb[w] = x;
+    for (Part &pt : s.parts) {
+        Request &r = *pt.r;
+        const uint64_t np = pt.pb - pt.pa;
+        if (!r.cancelled && np) {
+            if (!pt.counts_direct)
+                std::memcpy(r.counts() + pt.pa, counts + pt.fused_base, np * 4);
+            or_bits(r.bits(), pt.pa, bits, pt.fused_base, np);
+            if (status & GRIM_FLAG_BIN_RANGE) {  // only then look for -1 in this part
+                const int32_t *c = r.counts() + pt.pa;
+                for (uint64_t k = 0; k < np; ++k)
+                    if (c[k] < 0) {
+                        r.flags |= GRIM_FLAG_BIN_RANGE;
+                        break;
+                    }
             }
-            if (r.n_pairs & 31)
-                rb[nw - 1] &= (1u << (r.n_pairs & 31)) - 1u;
-            bool bad = false;
-            if (status & GRIM_FLAG_BIN_RANGE) {  // only then look for -1 in this request
-                const int32_t *c = r.counts();
-                for (uint64_t k = 0; k < r.n_pairs && !bad; ++k)
-                    bad = c[k] < 0;
-            }
-            r.flags = bad ? GRIM_FLAG_BIN_RANGE : 0u;
-            r.status = bad ? GRIM_E_BIN_RANGE : GRIM_OK;
-            if (bad)
-                ++failed;
-            ++completed;
-            pairs_done += r.n_pairs;
-            lat.push_back(ms_between(r.t_submit, now));
-        } else {
-            r.status = GRIM_E_CANCELLED;
-            ++cancelled;
         }
-        r.t_done = now;
-        r.state = State::Done;
-        --inflight_reqs;
+        part_closed(r, now);
     }
     pool->release(s.dev_off, s.lay.total);
-    s.reqs.clear();
-    s.pair_base.clear();
-    s.counts_direct.clear();
+    s.parts.clear();
     s.busy = false;
     if (--running_ticks == 0)
         busy_s += std::chrono::duration<double>(now - busy_since).count();
@@ -424,48 +479,109 @@ bool grim_server::launch_tick(std::unique_lock<std::mutex> &lk)
         }
     if (!slot || queue.empty())
         return false;
-    // admission: FIFO prefix with the head's e_den, within slots, pairs, budget
-    std::vector<std::shared_ptr<Request>> take;
-    uint64_t words = 0, reads = 0, pairs = 0;
-    const uint32_t e_den = queue.front()->e_den;
+    // admission: requests in arrival order with the e_den of the first one
+    // taken, within max_inflight, the tick's pair limit and the free budget; the
+    // request that does not fit the pair limit whole contributes the reads that
+    // do (at least one read when the tick would be empty) and stays queued.  A
+    // request already running in n_streams - 1 parts is passed over, so that
+    // one stream always remains for the requests behind it.
+    std::vector<Part> take;
+    uint64_t words = 0, reads = 0, pairs = 0, new_reqs = 0;
+    uint32_t e_den = 0;
+    const uint32_t max_parts = slots.size() > 1 ? (uint32_t)slots.size() - 1 : 1u;
     const uint64_t free_bytes = cfg.hbm_budget_bytes - pool->used();
     for (auto it = queue.begin(); it != queue.end();) {
-        Request &r = **it;
-        if (r.e_den != e_den || inflight_reqs + take.size() >= cfg.max_inflight)
+        std::shared_ptr<Request> rp = *it;
+        Request &r = *rp;
+        const bool first = r.state == State::Queued;
+        if (!first && r.parts_open >= max_parts) {
+            ++it;
+            continue;
+        }
+        if (take.empty())
+            e_den = r.e_den;
+        if (r.e_den != e_den || (first && inflight_reqs + new_reqs >= cfg.max_inflight))
             break;
-        if (!take.empty() && pairs + r.n_pairs > cfg.max_tick_pairs)
-            break;
-        const uint64_t total = plan(words + r.n_words + 1, reads + r.n_reads, pairs + r.n_pairs,
-                                    ws_need(idx, pairs + r.n_pairs)).total;
+        const uint64_t room = cfg.max_tick_pairs > pairs ? cfg.max_tick_pairs - pairs : 0;
+        const uint64_t *co = r.cand_off();
+        Part pt;
+        pt.r = rp;
+        pt.ra = r.next_read;
+        if (r.n_reads == 0) {
+            pt.rb = 0;
+        } else {
+            // last read end rb with co[rb] - co[ra] <= room
+            const uint64_t lim = co[pt.ra] + room;
+            const uint64_t *e = std::upper_bound(co + pt.ra + 1, co + r.n_reads + 1, lim);
+            pt.rb = (uint64_t)(e - co) - 1;
+            if (pt.rb <= pt.ra) {
+                if (!take.empty())
+                    break;
+                pt.rb = pt.ra + 1;
+            }
+        }
+        pt.pa = r.n_reads ? co[pt.ra] : 0;
+        pt.pb = r.n_reads ? co[pt.rb] : 0;
+        if (pt.ra == 0 && pt.rb == r.n_reads) {
+            pt.wlo = 0;
+            pt.nw = r.n_words;
+        } else {
+            uint64_t lo = ~0ull, hi = 0;
+            const uint64_t *ro = r.read_off();
+            const uint32_t *rl = r.read_len();
+            for (uint64_t i = pt.ra; i < pt.rb; ++i) {
+                lo = std::min<uint64_t>(lo, ro[i] >> 4);
+                hi = std::max<uint64_t>(hi, (ro[i] + rl[i] + 15) >> 4);
+            }
+            hi = std::min<uint64_t>(std::max(hi, lo), r.n_words);
+            pt.wlo = lo;
+            pt.nw = hi - lo;
+        }
+        const uint64_t np = pt.pb - pt.pa, nr = pt.rb - pt.ra;
+        const uint64_t total =
+            plan(words + pt.nw + 1, reads + nr, pairs + np, ws_need(idx, pairs + np)).total;
         if (total > free_bytes)
             break;
-        take.push_back(*it);
-        words += r.n_words;
-        reads += r.n_reads;
-        pairs += r.n_pairs;
-        it = queue.erase(it);
+        words += pt.nw;
+        reads += nr;
+        pairs += np;
+        if (first)
+            ++new_reqs;
+        take.push_back(pt);
+        if (pt.rb == r.n_reads) {
+            it = queue.erase(it);
+        } else {
+            // the rest of the request waits for the next tick
+            break;
+        }
     }
     if (take.empty())
         return false;
     Layout lay = plan(words + 1, reads, pairs, ws_need(idx, pairs));
     uint64_t off = 0;
     if (!pool->alloc(lay.total, &off)) {
-        // fragmented: put the requests back and wait for a tick to retire
+        // fragmented: nothing was admitted; put the erased requests back in order
         for (auto it = take.rbegin(); it != take.rend(); ++it)
-            queue.push_front(*it);
+            if (it->rb == it->r->n_reads)
+                queue.push_front(it->r);
         return false;
     }
     peak_bytes = std::max(peak_bytes, pool->used());
     const uint64_t tick = next_tick++;
     const auto now = Clock::now();
-    for (auto &r : take) {
-        r->state = State::Running;
-        r->t_admit = now;
-        r->tick = tick;
+    for (auto &pt : take) {
+        Request &r = *pt.r;
+        if (r.state == State::Queued) {
+            r.state = State::Running;
+            r.t_admit = now;
+            ++inflight_reqs;
+        }
+        r.tick = tick;
+        r.next_read = pt.rb;
+        r.all_admitted = pt.rb == r.n_reads;
+        ++r.parts_open;
     }
-    inflight_reqs += take.size();
     slot->busy = true;
-    slot->reqs = take;
     slot->lay = lay;
     slot->dev_off = off;
     slot->tick = tick;
@@ -489,8 +605,6 @@ bool grim_server::launch_tick(std::unique_lock<std::mutex> &lk)
             slot->stage_bytes = nb;
         }
     }
-    slot->pair_base.clear();
-    slot->counts_direct.assign(take.size(), 0);
     if (rc == GRIM_OK) {
         uint8_t *h = slot->stage;
         uint8_t *d = pool_base + off;
@@ -499,21 +613,26 @@ bool grim_server::launch_tick(std::unique_lock<std::mutex> &lk)
         uint64_t wbase = 0, rbase = 0, pbase = 0;
         uint64_t *ro = reinterpret_cast<uint64_t *>(h + lay.read_off);
         uint64_t *coff = reinterpret_cast<uint64_t *>(h + lay.cand_off);
-        for (auto &rp : take) {
-            Request &r = *rp;
-            cw.add(lay.words + wbase * 4, r.words(), r.n_words * 4);
+        for (auto &pt : take) {
+            Request &r = *pt.r;
+            const uint64_t nr = pt.rb - pt.ra, np = pt.pb - pt.pa;
+            cw.add(lay.words + wbase * 4, r.words() + pt.wlo, pt.nw * 4);
             const uint64_t *sro = r.read_off(), *sco = r.cand_off();
-            for (uint64_t i = 0; i < r.n_reads; ++i) {
-                ro[rbase + i] = sro[i] + wbase * 16;
-                coff[rbase + i] = sco[i] + pbase;
+            const uint64_t shift = wbase * 16, base0 = pt.wlo * 16;
+            for (uint64_t i = 0; i < nr; ++i) {
+                ro[rbase + i] = sro[pt.ra + i] - base0 + shift;
+                coff[rbase + i] = sco[pt.ra + i] - pt.pa + pbase;
             }
-            cl.add(lay.read_len + rbase * 4, r.read_len(), r.n_reads * 4);
-            ce.add(lay.read_e + rbase * 4, r.read_e(), r.n_reads * 4);
-            cb.add(lay.cand_bin + pbase * 4, r.cand_bin(), r.n_pairs * 4);
-            slot->pair_base.push_back(pbase);
-            wbase += r.n_words;
-            rbase += r.n_reads;
-            pbase += r.n_pairs;
+            if (nr) {
+                cl.add(lay.read_len + rbase * 4, r.read_len() + pt.ra, nr * 4);
+                ce.add(lay.read_e + rbase * 4, r.read_e() + pt.ra, nr * 4);
+            }
+            if (np)
+                cb.add(lay.cand_bin + pbase * 4, r.cand_bin() + pt.pa, np * 4);
+            pt.fused_base = pbase;
+            wbase += pt.nw;
+            rbase += nr;
+            pbase += np;
         }
         coff[rbase] = pbase;
         const uint32_t zero = 0;
@@ -550,8 +669,8 @@ bool grim_server::launch_tick(std::unique_lock<std::mutex> &lk)
         uint32_t *dbits = reinterpret_cast<uint32_t *>(dout + lay.bits);
         if (rc == GRIM_OK)
             rc = grim_filter_batch(idx, &b, dcounts, dbits, d + lay.ws, lay.ws_bytes, nullptr, st);
-        // results: large count slices straight into the request's block, the
-        // rest (small slices, all pass bits, the status word) via the stage
+        // results: large count slices straight into the request's result area,
+        // the rest (small slices, all pass bits, the status word) via the stage
         if (rc == GRIM_OK) {
             uint64_t run_lo = 0, run_hi = 0;
             bool run = false;
@@ -562,12 +681,13 @@ bool grim_server::launch_tick(std::unique_lock<std::mutex> &lk)
                 run = false;
             };
             for (size_t j = 0; j < take.size() && e == hipSuccess; ++j) {
-                Request &r = *take[j];
-                const uint64_t lo = lay.counts + slot->pair_base[j] * 4, nb = r.n_pairs * 4;
+                Part &pt = take[j];
+                const uint64_t lo = lay.counts + pt.fused_base * 4, nb = (pt.pb - pt.pa) * 4;
                 if (nb >= kDirectBytes) {
                     flush();
-                    e = hipMemcpyAsync(r.counts(), dout + lo, nb, hipMemcpyDeviceToHost, st);
-                    slot->counts_direct[j] = 1;
+                    e = hipMemcpyAsync(pt.r->counts() + pt.pa, dout + lo, nb,
+                                       hipMemcpyDeviceToHost, st);
+                    pt.counts_direct = true;
                 } else if (nb) {
                     if (run && lo == run_hi) {
                         run_hi = lo + nb;
@@ -593,22 +713,26 @@ bool grim_server::launch_tick(std::unique_lock<std::mutex> &lk)
     }
     lk.lock();
     if (rc != GRIM_OK) {
-        // the tick never completed on the device: fail its requests
+        // the tick never completed on the device: fail its requests (a request
+        // with reads still queued is dropped from the queue)
         (void)hipStreamSynchronize(slot->stream);
         const auto t = Clock::now();
-        for (auto &r : take) {
-            r->status = rc;
-            r->state = State::Done;
-            r->t_done = t;
-            ++failed;
-            --inflight_reqs;
+        for (auto &pt : take) {
+            Request &r = *pt.r;
+            if (!r.all_admitted) {
+                drop_from_queue(r);
+                r.all_admitted = true;
+            }
+            r.status = rc;
+            part_closed(r, t);
         }
         pool->release(off, lay.total);
-        slot->reqs.clear();
         slot->busy = false;
         if (--running_ticks == 0)
             busy_s += std::chrono::duration<double>(t - busy_since).count();
         cv_done.notify_all();
+    } else {
+        slot->parts = std::move(take);
     }
     return true;
 }
@@ -788,6 +912,7 @@ extern "C" int grim_serve_submit(grim_server_t *s, const grim_batch_t *b, uint64
         *reinterpret_cast<uint64_t *>(h + r->lay.cand_off) = 0;
     }
     par_memcpy(h + r->lay.cand_bin, b->cand_bin, P * 4);
+    std::memset(h + r->lay.bits, 0, ((P + 31) / 32) * 4);  // parts OR their bits in
     r->e_den = b->e_den;
     r->n_words = nwords;
     r->n_reads = n;
@@ -818,6 +943,8 @@ extern "C" int grim_serve_submit_inplace(grim_server_t *s, const grim_batch_t *b
     r->p_cand_bin = b->cand_bin;
     r->p_counts = counts;
     r->p_bits = pass_bits;
+    if (P)
+        std::memset(pass_bits, 0, ((P + 31) / 32) * 4);  // parts OR their bits in
     r->e_den = b->e_den;
     r->n_words = n ? b->n_read_words : 0;
     r->n_reads = n;
@@ -904,16 +1031,20 @@ extern "C" int grim_serve_cancel(grim_server_t *s, uint64_t ticket)
         return GRIM_OK;
     r.cancelled = true;
     if (r.state == State::Queued) {
-        for (auto q = s->queue.begin(); q != s->queue.end(); ++q)
-            if ((*q)->ticket == ticket) {
-                s->queue.erase(q);
-                break;
-            }
+        s->drop_from_queue(r);
         r.status = GRIM_E_CANCELLED;
         r.state = State::Done;
         r.t_done = Clock::now();
         ++s->cancelled;
         s->cv_done.notify_all();
+    } else if (!r.all_admitted) {
+        // admitted in part: the rest never runs; done once its parts in flight retire
+        s->drop_from_queue(r);
+        r.all_admitted = true;
+        if (r.parts_open == 0) {
+            s->part_closed(r, Clock::now());
+            s->cv_done.notify_all();
+        }
     }
     return GRIM_OK;
 }

@@ -227,3 +227,57 @@ def test_inplace_submission_matches_alone(setup):
         if i % 3:
             assert np.array_equal(pinned[i].out_counts[:c2.size], c2)
     srv.destroy()
+
+
+def test_requests_split_into_parts(setup):
+    """Requests with more pairs than max_tick_pairs run in parts of whole reads
+    (at 100 pairs down to single reads with more candidates than the limit):
+    every request equals its solo run, in place and copied, and an invalid bin
+    id fails only its own request."""
+    g, w, idx = setup
+    reqs = make_requests(g, w, 24, 17, max_reads=1500)
+    bad_sub, _ = reqs[5]
+    bad_sub["cand_bin"][len(bad_sub["cand_bin"]) - 2] = idx.n_bins + 1
+    reqs[5] = (bad_sub, g.HostBatch(bad_sub["codes"], bad_sub["read_off"], bad_sub["read_len"],
+                                    bad_sub["read_e"], bad_sub["e_den"], bad_sub["cand_off"],
+                                    bad_sub["cand_bin"], max_len=256))
+    solo = [alone(g, idx, sub) for sub, _ in reqs]
+    pinned = [g.HostBatch(sub["codes"], sub["read_off"], sub["read_len"], sub["read_e"],
+                          sub["e_den"], sub["cand_off"], sub["cand_bin"], max_len=256, pinned=True)
+              for sub, _ in reqs]
+    for tick_pairs in (3000, 100):
+        srv = g.Server(idx, hbm_budget_bytes=64 << 20, max_inflight=8, n_streams=3,
+                       max_tick_pairs=tick_pairs, max_len=256)
+        ts = [srv.submit_inplace(pinned[i]) if i % 2 else srv.submit(hb)
+              for i, (_, hb) in enumerate(reqs)]
+        for i, t in enumerate(ts):
+            rc, c, b, st = srv.wait(t)
+            assert rc == solo[i][0], (tick_pairs, i, rc)
+            assert np.array_equal(c, solo[i][1]), f"{tick_pairs}: request {i} counts"
+            assert np.array_equal(b, solo[i][2]), f"{tick_pairs}: request {i} pass bits"
+        s = srv.stats()
+        say("split", tick_pairs, s)
+        assert s["ticks"] > len(reqs), "no request was split"
+        assert s["completed"] == len(reqs)
+        srv.destroy()
+
+
+def test_cancel_request_running_in_parts(setup):
+    """A request cancelled while its parts run: the rest never runs, the ticket
+    reports GRIM_E_CANCELLED, and the server goes on serving."""
+    g, w, idx = setup
+    sub, hb = cut(g, w, 0, 6000)
+    say("pairs", hb.n_pairs)
+    srv = g.Server(idx, hbm_budget_bytes=64 << 20, n_streams=1, max_tick_pairs=2000, max_len=256)
+    t = srv.submit(hb)
+    time.sleep(0.002)
+    srv.cancel(t)
+    rc, c, b, st = srv.wait(t)
+    assert rc == g.GRIM_E_CANCELLED
+    sub2, hb2 = cut(g, w, 100, 400)
+    rc2, c2, b2, _ = srv.wait(srv.submit(hb2))
+    solo = alone(g, idx, sub2)
+    assert rc2 == 0 and np.array_equal(c2, solo[1]) and np.array_equal(b2, solo[2])
+    s = srv.stats()
+    assert s["cancelled"] == 1 and s["completed"] == 1
+    srv.destroy()
