@@ -425,23 +425,40 @@ def grim_tune(index, batch, counts, pass_bits, workspace, stream=None):
     return t
 
 
-def grim_compact_survivors(batch, pass_bits, capacity=None, stream=None):
+def grim_survivors_workspace_size(n_pairs):
+    nb = _u64()
+    _check(_lib.grim_survivors_workspace_size(int(n_pairs), ctypes.byref(nb)),
+           "grim_survivors_workspace_size")
+    return int(nb.value)
+
+
+def grim_compact_survivors(batch, pass_bits, capacity=None, stream=None, out=None,
+                           workspace=None, read_total=True):
     """Survivor list of a filtered batch: (surv_pair, surv_read, surv_bin, n_total)
-    device tensors, truncated to min(total, capacity)."""
+    device tensors, truncated to min(total, capacity).  out = (surv_pair int64,
+    surv_read int32, surv_bin int32, n int64[1]) reuses caller tensors (capacity =
+    their length); read_total=False skips the host read-back of the total and
+    returns the untruncated tensors with the device count tensor last."""
     torch = _torch()
     dev = pass_bits.device
-    cap = batch.n_pairs if capacity is None else int(capacity)
-    sp = torch.empty(max(1, cap), dtype=torch.int64, device=dev)
-    sr = torch.empty(max(1, cap), dtype=torch.int32, device=dev)
-    sb = torch.empty(max(1, cap), dtype=torch.int32, device=dev)
-    n = torch.zeros(1, dtype=torch.int64, device=dev)
-    nb = _u64()
-    _check(_lib.grim_survivors_workspace_size(batch.n_pairs, ctypes.byref(nb)),
-           "grim_survivors_workspace_size")
-    ws = torch.empty(int(nb.value), dtype=torch.uint8, device=dev)
+    if out is not None:
+        sp, sr, sb, n = out
+        cap = int(sp.numel())
+    else:
+        cap = batch.n_pairs if capacity is None else int(capacity)
+        sp = torch.empty(max(1, cap), dtype=torch.int64, device=dev)
+        sr = torch.empty(max(1, cap), dtype=torch.int32, device=dev)
+        sb = torch.empty(max(1, cap), dtype=torch.int32, device=dev)
+        n = torch.zeros(1, dtype=torch.int64, device=dev)
+    ws = workspace
+    if ws is None:
+        ws = torch.empty(grim_survivors_workspace_size(batch.n_pairs), dtype=torch.uint8,
+                         device=dev)
     _check(_lib.grim_compact_survivors(ctypes.byref(batch.c), _ptr(pass_bits), cap, _ptr(sp),
                                        _ptr(sr), _ptr(sb), _ptr(n), _ptr(ws), ws.numel(),
                                        _stream(stream)), "grim_compact_survivors")
+    if not read_total:
+        return sp, sr, sb, n
     total = int(n.item())
     k = min(total, cap)
     return sp[:k], sr[:k], sb[:k], total

@@ -105,6 +105,25 @@ __global__ __launch_bounds__(1024) void compact_scan_kernel(uint64_t *sums, uint
         *n_out = carry_s;
 }
 
+// Read holding pair k: the last r in [lo, hi] with off[r] <= k (off[lo] <= k).
+template <typename Off>
+__device__ __forceinline__ uint64_t read_of(const Off *off, uint64_t lo, uint64_t hi, uint64_t k)
+{
+    while (lo < hi) {
+        const uint64_t mid = (lo + hi + 1) >> 1;
+        if ((uint64_t)off[mid] <= k)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// Offsets staged in LDS per workgroup: a workgroup covers 32768 pairs, and the
+// reads they belong to (one search each for the first and the last pair) are
+// looked up in LDS when there are at most kStageReads of them.
+constexpr int kStageReads = 2048;
+
 __global__ __launch_bounds__(256) void compact_emit_kernel(
     const uint32_t *__restrict__ bits, uint64_t n_words, uint64_t n_pairs,
     const uint64_t *__restrict__ block_off, const uint64_t *__restrict__ cand_off, uint64_t n_reads,
@@ -112,6 +131,8 @@ __global__ __launch_bounds__(256) void compact_emit_kernel(
     uint32_t *__restrict__ surv_read, uint32_t *__restrict__ surv_bin)
 {
     __shared__ uint32_t lds[4];
+    __shared__ uint64_t stage[kStageReads + 1];
+    __shared__ uint64_t range[2];
     const uint64_t w0 = (uint64_t)blockIdx.x * kCompactWpb + (uint64_t)threadIdx.x * kCompactWpt;
     uint32_t x[kCompactWpt];
     uint32_t c = 0;
@@ -122,23 +143,41 @@ __global__ __launch_bounds__(256) void compact_emit_kernel(
     }
     uint32_t total;
     uint64_t pos = block_off[blockIdx.x] + block_exclusive_scan(c, lds, &total);
-    if (c == 0 || n_reads == 0)
+    if (total == 0 || n_reads == 0)
         return;
-    // read of the first survivor: the last r with cand_off[r] <= pair
+    // reads of the workgroup's first and last pair
+    const uint64_t p_first = (uint64_t)blockIdx.x * kCompactWpb * 32;
+    const uint64_t p_end = p_first + (uint64_t)kCompactWpb * 32 < n_pairs
+                               ? p_first + (uint64_t)kCompactWpb * 32 : n_pairs;
+    if (threadIdx.x < 2)
+        range[threadIdx.x] =
+            read_of(cand_off, 0, n_reads - 1, threadIdx.x == 0 ? p_first : p_end - 1);
+    __syncthreads();
+    const uint64_t r_lo = range[0], r_hi = range[1];
+    const bool staged = r_hi - r_lo + 1 <= (uint64_t)kStageReads;
+    if (staged) {
+        // offsets of reads r_lo .. r_hi + 1 (the last one bounds the walk)
+        const uint64_t n_st = r_hi - r_lo + 2;
+        for (uint64_t i = threadIdx.x; i < n_st; i += blockDim.x)
+            stage[i] = r_lo + i <= n_reads ? cand_off[r_lo + i] : ~0ull;
+    }
+    __syncthreads();
+    if (c == 0)
+        return;
     uint64_t first = 0;
 #pragma unroll
     for (int j = kCompactWpt - 1; j >= 0; --j)
         if (x[j])
             first = (w0 + j) * 32 + (__ffs(x[j]) - 1);
-    uint64_t lo = 0, hi = n_reads - 1;
-    while (lo < hi) {
-        const uint64_t mid = (lo + hi + 1) >> 1;
-        if (cand_off[mid] <= first)
-            lo = mid;
-        else
-            hi = mid - 1;
+    // r: the read holding the current pair; nxt: where the next read starts
+    uint64_t r, nxt;
+    if (staged) {
+        r = r_lo + read_of(stage, 0, r_hi - r_lo, first);
+        nxt = stage[r - r_lo + 1];
+    } else {
+        r = read_of(cand_off, r_lo, r_hi, first);
+        nxt = r + 1 <= n_reads ? cand_off[r + 1] : ~0ull;
     }
-    uint64_t r = lo;
 #pragma unroll
     for (int j = 0; j < kCompactWpt; ++j) {
         uint32_t m = x[j];
@@ -146,8 +185,10 @@ __global__ __launch_bounds__(256) void compact_emit_kernel(
             const uint32_t b = __ffs(m) - 1;
             m &= m - 1;
             const uint64_t k = (w0 + j) * 32 + b;
-            while (r + 1 < n_reads && cand_off[r + 1] <= k)
+            while (nxt <= k && r + 1 < n_reads) {
                 ++r;
+                nxt = staged ? stage[r - r_lo + 1] : cand_off[r + 1];
+            }
             if (pos < cap) {
                 surv_pair[pos] = k;
                 surv_read[pos] = (uint32_t)r;

@@ -75,6 +75,33 @@ def test_survivors_edges():
     assert total == 0
 
 
+def test_survivors_many_reads_per_block():
+    """Workgroups of the emit pass cover 32768 pairs; stretches of reads with
+    0-2 candidates put more reads in one workgroup than its staged offsets hold
+    (then the reads are searched in global memory), stretches of long candidate
+    lists few; both against the oracle, for sparse and dense pass patterns."""
+    g = lib()
+    rng = np.random.default_rng(9)
+    parts = [rng.integers(0, 3, 60_000), rng.integers(100, 4097, 60),
+             rng.integers(0, 2, 40_000), np.zeros(5000, np.int64), rng.integers(0, 40, 3000)]
+    k = np.concatenate(parts).astype(np.uint32)
+    n_reads = k.size
+    off = gs.offsets_from_counts(k)
+    n = int(off[-1])
+    w = dict(codes=np.zeros(n_reads * 10, np.uint8),
+             read_off=np.arange(n_reads, dtype=np.uint64) * 10,
+             read_len=np.full(n_reads, 10, np.uint32), read_e=np.zeros(n_reads, np.uint32),
+             e_den=10000, cand_off=off, cand_bin=rng.integers(0, 1 << 30, n).astype(np.uint32))
+    for density in (0.015, 0.5):
+        p = (rng.random(n) < density).astype(np.uint8)
+        words = oracle.pack_bitmask(p)
+        want = oracle.survivors(words, n, off, w["cand_bin"])
+        sp, sr, sb, total = _compact(g, w, words)
+        assert total == want[0].size
+        assert np.array_equal(sp, want[0]) and np.array_equal(sr, want[1]) and \
+            np.array_equal(sb, want[2]), density
+
+
 def _verify_gpu(g, idx, w, surv_read, surv_bin, max_len=None):
     import torch
     batch = g.Batch.from_workload(w, max_len=max_len)
