@@ -242,17 +242,60 @@ __device__ __forceinline__ uint32_t base_at(const uint32_t *__restrict__ w, uint
     return (x >> (30 - 2 * (uint32_t)(p & 15))) & 3u;
 }
 
+// 16 reference bases starting at p (any alignment), first base in the top bits.
+__device__ __forceinline__ uint32_t ref_window(const uint32_t *__restrict__ w, uint64_t nw, uint64_t p)
+{
+    const uint64_t wi = p >> 4;
+    const uint32_t sh = (uint32_t)(p & 15) << 1;
+    const uint32_t w0 = wi < nw ? w[wi] : 0u;
+    const uint32_t w1 = wi + 1 < nw ? w[wi + 1] : 0u;
+    return sh ? (w0 << sh) | (w1 >> (32 - sh)) : w0;
+}
+
+// A workgroup takes 256 survivors at a time and hands them to its threads
+// sorted by the number of 64-row blocks of their read (counting sort in LDS),
+// so that most wavefronts hold reads of one block count and skip the blocks
+// none of their lanes has; pass bits of the 256 are gathered in LDS and
+// stored as 8 whole words.
 template <int W>
 __global__ __launch_bounds__(256) void verify_kernel(VerifyArgs a)
 {
-    const int lane = threadIdx.x & 63;
-    const uint64_t stride = (uint64_t)gridDim.x * (blockDim.x >> 6) * 64;
-    for (uint64_t base = ((uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 64;
-         base < a.n_surv; base += stride) {
-        const uint64_t i = base + lane;
-        int32_t d = -1;
-        bool ok = false;
+    __shared__ uint32_t order[256];
+    __shared__ uint32_t cls[W + 1];
+    __shared__ uint32_t okw[8];
+    const int t = threadIdx.x;
+    const uint64_t stride = (uint64_t)gridDim.x * 256;
+    const uint64_t n_words = (a.n_surv + 31) / 32;
+    for (uint64_t base = (uint64_t)blockIdx.x * 256; base < a.n_surv; base += stride) {
+        // block count of survivor base + t (0 when there is nothing to align)
+        int key = 0;
+        {
+            const uint64_t i = base + t;
+            if (i < a.n_surv) {
+                const uint32_t r = a.surv_read[i];
+                if (r < a.n_reads) {
+                    const uint32_t L = a.read_len[r];
+                    key = L <= 64u * W ? (int)((L + 63) >> 6) : 0;
+                }
+            }
+        }
+        if (t <= W)
+            cls[t] = 0;
+        if (t < 8)
+            okw[t] = 0;
+        __syncthreads();
+        const uint32_t rank = atomicAdd(&cls[key], 1u);
+        __syncthreads();
+        uint32_t start = 0;
+        for (int c = 0; c < key; ++c)
+            start += cls[c];
+        order[start + rank] = (uint32_t)t;
+        __syncthreads();
+        const uint32_t slot = order[t];
+        const uint64_t i = base + slot;
         if (i < a.n_surv) {
+            int32_t d = -1;
+            bool ok = false;
             const uint32_t r = a.surv_read[i], b = a.surv_bin[i];
             const uint64_t nb = a.nw * 16;
             const uint32_t L = r < a.n_reads ? a.read_len[r] : 0u;
@@ -284,9 +327,14 @@ __global__ __launch_bounds__(256) void verify_kernel(VerifyArgs a)
                 uint64_t hi = lo + a.B + a.O;
                 if (hi > a.G)
                     hi = a.G;
+                const uint64_t span = hi > lo ? hi - lo : 0;
                 int32_t score = (int32_t)L, best = (int32_t)L;
-                for (uint64_t j = lo; j < hi; ++j) {
-                    const uint32_t cb = base_at(a.ref, a.ref_words, j);
+                uint32_t win = 0;
+                for (uint64_t j = 0; j < span; ++j) {
+                    if ((j & 15) == 0)
+                        win = ref_window(a.ref, a.ref_words, lo + j);
+                    const uint32_t cb = win >> 30;
+                    win <<= 2;
                     int h = 0;
 #pragma unroll
                     for (int w = 0; w < W; ++w) {
@@ -318,13 +366,13 @@ __global__ __launch_bounds__(256) void verify_kernel(VerifyArgs a)
                 ok = best <= (int32_t)E;
             }
             a.dist[i] = d;
+            if (ok)
+                atomicOr(&okw[slot >> 5], 1u << (slot & 31));
         }
-        const uint64_t m = __ballot(ok);
-        const uint64_t n_words = (a.n_surv + 31) / 32;
-        if (lane == 0)
-            a.ok_bits[base >> 5] = (uint32_t)m;
-        if (lane == 32 && (base >> 5) + 1 < n_words)
-            a.ok_bits[(base >> 5) + 1] = (uint32_t)(m >> 32);
+        __syncthreads();
+        if (t < 8 && (base >> 5) + t < n_words)
+            a.ok_bits[(base >> 5) + t] = okw[t];
+        __syncthreads();
     }
 }
 
