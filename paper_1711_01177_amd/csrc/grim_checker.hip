@@ -263,6 +263,10 @@ __global__ __launch_bounds__(256) void verify_kernel(VerifyArgs a)
     __shared__ uint32_t order[256];
     __shared__ uint32_t cls[W + 1];
     __shared__ uint32_t okw[8];
+    // match masks of every thread's read: peq[(base * W + block) * 256 + thread]
+    // (lane-interleaved, so that a wavefront's reads of one column are
+    // conflict-free whatever bases its lanes see)
+    __shared__ uint64_t peq[4 * W * 256];
     const int t = threadIdx.x;
     const uint64_t stride = (uint64_t)gridDim.x * 256;
     const uint64_t n_words = (a.n_surv + 31) / 32;
@@ -303,10 +307,10 @@ __global__ __launch_bounds__(256) void verify_kernel(VerifyArgs a)
             if (r < a.n_reads && b < a.n_bins && L <= 64u * W && off <= nb && L <= nb - off) {
                 const uint32_t E =
                     (uint32_t)(((uint64_t)a.read_e[r] * L + a.e_den - 1) / a.e_den);
-                uint64_t pa[W], pc[W], pg[W], pt[W], Pv[W], Mv[W];
+                uint64_t Pv[W], Mv[W];
 #pragma unroll
                 for (int w = 0; w < W; ++w) {
-                    pa[w] = pc[w] = pg[w] = pt[w] = 0;
+                    uint64_t pa = 0, pc = 0, pg = 0, pt = 0;
                     Pv[w] = ~0ull;
                     Mv[w] = 0;
                     for (uint32_t k = 0; k < 64; ++k) {
@@ -315,11 +319,15 @@ __global__ __launch_bounds__(256) void verify_kernel(VerifyArgs a)
                             break;
                         const uint32_t cb = base_at(a.rw, a.nw, off + p);
                         const uint64_t bit = 1ull << k;
-                        pa[w] |= cb == 0 ? bit : 0ull;
-                        pc[w] |= cb == 1 ? bit : 0ull;
-                        pg[w] |= cb == 2 ? bit : 0ull;
-                        pt[w] |= cb == 3 ? bit : 0ull;
+                        pa |= cb == 0 ? bit : 0ull;
+                        pc |= cb == 1 ? bit : 0ull;
+                        pg |= cb == 2 ? bit : 0ull;
+                        pt |= cb == 3 ? bit : 0ull;
                     }
+                    peq[(0 * W + w) * 256 + t] = pa;
+                    peq[(1 * W + w) * 256 + t] = pc;
+                    peq[(2 * W + w) * 256 + t] = pg;
+                    peq[(3 * W + w) * 256 + t] = pt;
                 }
                 const int wu = (int)((L + 63) >> 6);
                 const uint64_t hb = 1ull << ((L - 1) & 63);
@@ -335,11 +343,12 @@ __global__ __launch_bounds__(256) void verify_kernel(VerifyArgs a)
                         win = ref_window(a.ref, a.ref_words, lo + j);
                     const uint32_t cb = win >> 30;
                     win <<= 2;
+                    const uint64_t *pq = peq + cb * W * 256 + t;
                     int h = 0;
 #pragma unroll
                     for (int w = 0; w < W; ++w) {
                         if (w < wu) {
-                            uint64_t eq = cb == 0 ? pa[w] : cb == 1 ? pc[w] : cb == 2 ? pg[w] : pt[w];
+                            uint64_t eq = pq[w * 256];
                             const uint64_t xv = eq | Mv[w];
                             if (h < 0)
                                 eq |= 1ull;
