@@ -322,9 +322,9 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: the filter shards by replicating the index and "
-              "splitting reads, with no exchange, and multi-GPU runs are not part of this build",
-              file=sys.stderr)
+        print("bench.py measures one GPU only: the filter would shard by replicating the "
+              "index and splitting reads across GPUs, with no exchange, and runs on several "
+              "GPUs are not supported", file=sys.stderr)
         sys.exit(2)
 
     import torch

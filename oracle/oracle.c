@@ -13,7 +13,7 @@
  * as the seeded generators emit them.  No 2-bit packing, no blocking, no
  * deduplication, no reordering: every step follows the paper's description.
  *
- * Readings of points the paper leaves open (each is also listed in the design doc):
+ * Readings of points the paper leaves open:
  *   - token value: first base most significant, tok = sum_j code[j]*4^(q-1-j)
  *   - bin b covers ref[b*B, min(G, (b+1)*B + O)); B is the stride, O the extra
  *     overlap; only tokens lying wholly inside that range are recorded
