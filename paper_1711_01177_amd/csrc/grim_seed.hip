@@ -195,14 +195,19 @@ __global__ __launch_bounds__(256) void seed_count_kernel(
     }
 }
 
-// one wavefront per read
+// One wavefront per read; its seeds are looked up 8 at a time, one group of 8
+// lanes per seed, and each group copies its seed's hits (seed order, then index
+// order, as the count pass assumed) to the read's hit range.
+constexpr int kSeedGroup = 8;                 // lanes per seed
+constexpr int kSeedsPerStep = kWave / kSeedGroup;
+
 __global__ __launch_bounds__(256) void seed_emit_kernel(
     const uint32_t *__restrict__ rw, uint64_t nw, const uint64_t *__restrict__ read_off,
     const uint32_t *__restrict__ read_len, uint64_t n_reads, uint32_t k,
     const uint64_t *__restrict__ idx_off, const uint32_t *__restrict__ idx_pos, uint64_t G,
     uint64_t B, const uint64_t *__restrict__ hit_off, uint32_t *__restrict__ hit_bin)
 {
-    const int lane = threadIdx.x & 63;
+    const int lane = threadIdx.x & 63, grp = lane / kSeedGroup, sub = lane % kSeedGroup;
     const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
     const uint64_t nb = nw * 16;
     for (uint64_t r = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); r < n_reads;
@@ -211,19 +216,38 @@ __global__ __launch_bounds__(256) void seed_emit_kernel(
         const uint64_t off = read_off[r];
         if (off > nb || L > nb - off)
             continue;
+        const uint32_t n_seeds = L >= k ? L / k : 0u;
         uint64_t dst = hit_off[r];
-        for (uint32_t o = 0; o + k <= L; o += k) {
-            const uint32_t km = kmer_at(rw, nw, off + o, k);
-            const uint64_t a = idx_off[km], b = idx_off[km + 1];
-            for (uint64_t h = a + lane; h < b; h += kWave) {
-                int64_t z = (int64_t)idx_pos[h] - (int64_t)o;
+        for (uint32_t s0 = 0; s0 < n_seeds; s0 += kSeedsPerStep) {
+            const uint32_t sd = s0 + (uint32_t)grp;
+            const uint32_t o = sd * k;
+            uint64_t a = 0, cnt = 0;
+            if (sd < n_seeds) {
+                const uint32_t km = kmer_at(rw, nw, off + o, k);
+                a = idx_off[km];
+                cnt = idx_off[km + 1] - a;
+            }
+            // exclusive prefix of the groups' hit counts (lane sub == 0 of each group)
+            uint64_t incl = sub == 0 ? cnt : 0;
+#pragma unroll
+            for (int d = 1; d < kWave; d <<= 1) {
+                const uint64_t y = __shfl_up(incl, d);
+                if (lane >= d)
+                    incl += y;
+            }
+            const uint64_t total = __shfl(incl, kWave - 1);
+            const uint64_t before = incl - (sub == 0 ? cnt : 0);
+            // the group's first lane holds its exclusive offset
+            const uint64_t gdst = dst + __shfl(before, grp * kSeedGroup);
+            for (uint64_t h = sub; h < cnt; h += kSeedGroup) {
+                int64_t z = (int64_t)idx_pos[a + h] - (int64_t)o;
                 if (z < 0)
                     z = 0;
                 if ((uint64_t)z > G - 1)
                     z = (int64_t)(G - 1);
-                hit_bin[dst + (h - a)] = (uint32_t)((uint64_t)z / B);
+                hit_bin[gdst + h] = (uint32_t)((uint64_t)z / B);
             }
-            dst += b - a;
+            dst += total;
         }
     }
 }
