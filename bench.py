@@ -106,7 +106,8 @@ def cpu_baseline(w, target_pairs, n_threads, idx=None):
 
 
 def serving_leg(g, idx, w, rng, loads=(0.25, 0.5, 0.75, 0.9), n_requests=10_000, pool=256,
-                max_reads=65536, inplace=True, tick_pairs=64 << 20, n_streams=3):
+                max_reads=65536, inplace=True, tick_pairs=64 << 20, n_streams=3,
+                fixed_rates=None):
     """Served latency.  A pool of `pool` requests of log-uniform size
     (1..max_reads reads) is cut from the workload.  First the server's capacity
     is measured closed-loop (a burst of requests submitted at once); then, for
@@ -117,7 +118,9 @@ def serving_leg(g, idx, w, rng, loads=(0.25, 0.5, 0.75, 0.9), n_requests=10_000,
     (results land in the request's pinned output buffers, so a buffer is in
     flight at most once at a time); False uses the copying submission.  Ticks
     hold at most tick_pairs pairs, so larger requests run in parts whose copies
-    and launches overlap on n_streams streams."""
+    and launches overlap on n_streams streams.  fixed_rates (pairs per second)
+    replaces the loads relative to capacity by absolute arrival rates, so that
+    server configurations can be compared at the same offered traffic."""
     n_reads = w["read_len"].size
     reqs = []
     for _ in range(pool):
@@ -160,8 +163,10 @@ def serving_leg(g, idx, w, rng, loads=(0.25, 0.5, 0.75, 0.9), n_requests=10_000,
                max_tick_pairs=tick_pairs, n_streams=n_streams,
                capacity_burst_s=walls,
                capacity_pairs_per_s=capacity, points=[])
-    for rho in loads:
-        rate = rho * capacity / mean_pairs          # requests per second
+    points = [(rho, rho * capacity) for rho in loads] if fixed_rates is None else \
+        [(r / capacity, r) for r in fixed_rates]
+    for rho, pair_rate in points:
+        rate = pair_rate / mean_pairs               # requests per second
         gaps = rng.exponential(1.0 / rate, size=n_requests)
         free = list(range(pool))
         flying = {}                                 # ticket -> pool entry
