@@ -621,6 +621,8 @@ def main():
                                                                args.tile or args.wg))},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     # counter-measured bytes of one launch over this run's step time
+                     "traffic_gbs": (traffic / (ms * 1e-3) / 1e9) if traffic else None,
                      "bytes_per_pair": bpp, "bytes_per_read": bpr,
                      "kernel": "filter_batched_kernel (+ worklist_kernel, in the same timing)"},
         "eager_ms_per_step": eager_ms,
