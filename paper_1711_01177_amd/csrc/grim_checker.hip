@@ -344,25 +344,29 @@ __global__ __launch_bounds__(256) void verify_kernel(VerifyArgs a)
                     const uint32_t cb = win >> 30;
                     win <<= 2;
                     const uint64_t *pq = peq + cb * W * 256 + t;
+                    // every block's mask for this base, read up front (entries of
+                    // blocks past the read's last are read but not used)
+                    uint64_t eqw[W];
+#pragma unroll
+                    for (int w = 0; w < W; ++w)
+                        eqw[w] = pq[w * 256];
                     int h = 0;
 #pragma unroll
                     for (int w = 0; w < W; ++w) {
                         if (w < wu) {
-                            uint64_t eq = pq[w * 256];
+                            // carry-in from the block above as two 0/1 words
+                            // (h is -1, 0 or +1), so no lane branches on it
+                            const uint64_t hm_in = (uint64_t)(h < 0), hp_in = (uint64_t)(h > 0);
+                            uint64_t eq = eqw[w];
                             const uint64_t xv = eq | Mv[w];
-                            if (h < 0)
-                                eq |= 1ull;
+                            eq |= hm_in;
                             const uint64_t xh = (((eq & Pv[w]) + Pv[w]) ^ Pv[w]) | eq;
                             uint64_t ph = Mv[w] | ~(xh | Pv[w]);
                             uint64_t mh = Pv[w] & xh;
                             const uint64_t top = (w == wu - 1) ? hb : (1ull << 63);
                             const int hout = (ph & top) ? 1 : ((mh & top) ? -1 : 0);
-                            ph <<= 1;
-                            mh <<= 1;
-                            if (h < 0)
-                                mh |= 1ull;
-                            else if (h > 0)
-                                ph |= 1ull;
+                            ph = (ph << 1) | hp_in;
+                            mh = (mh << 1) | hm_in;
                             Pv[w] = mh | ~(xv | ph);
                             Mv[w] = ph & xv;
                             h = hout;
