@@ -323,6 +323,8 @@ def main():
     ap.add_argument("--wg", type=int, default=0)
     ap.add_argument("--cpu-pairs", type=float, default=3.0e8)
     ap.add_argument("--no-window", action="store_true", help="skip the bin-window leg")
+    ap.add_argument("--no-probe", action="store_true",
+                    help="skip the memory-ceiling probes (gather and streaming read)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
     args = ap.parse_args()
 
@@ -459,6 +461,38 @@ def main():
     alg_bytes = n_pairs * bpp + n_reads * bpr
     achieved = alg_bytes / (ms * 1e-3) / 1e9
     pairs_per_s = n_pairs / (ms * 1e-3)
+
+    # memory ceilings of the same accesses: the filter's gather without its
+    # token work (same bin ids, 4-byte result per pair), and a streaming read
+    probes = None
+    if not args.no_probe:
+        pout = torch.empty(max(1, n_pairs), dtype=torch.int32, device="cuda")
+        g.grim_probe_gather(idx, batch.cand_bin, pout, n=n_pairs)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(5):
+            g.grim_probe_gather(idx, batch.cand_bin, pout, n=n_pairs)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        gms = e0.elapsed_time(e1) / 5
+        del pout
+        sink = torch.zeros(1, dtype=torch.int32, device="cuda")
+        g.grim_probe_stream(idx, sink)
+        e0.record(stream)
+        for _ in range(5):
+            g.grim_probe_stream(idx, sink)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        sms = e0.elapsed_time(e1) / 5
+        vb = idx.bytes // idx.n_bins
+        gather_gbs = n_pairs * (vb + 8) / (gms * 1e-3) / 1e9
+        probes = dict(gather_ms=gms, gather_gbs=gather_gbs, gather_bytes_per_pair=vb + 8,
+                      stream_read_gbs=idx.bytes / (sms * 1e-3) / 1e9,
+                      filter_time_over_gather=ms / gms)
+        log(f"[bench] probes: gather of the same bin ids {gms:.3f} ms ({gather_gbs:.0f} GB/s), "
+            f"streaming read {probes['stream_read_gbs']:.0f} GB/s; filter / gather time "
+            f"{ms / gms:.3f}")
 
     plain = None
     if not args.no_plain:
@@ -623,9 +657,14 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      # counter-measured bytes of one launch over this run's step time
                      "traffic_gbs": (traffic / (ms * 1e-3) / 1e9) if traffic else None,
+                     # the same gather without the filter's work, measured in this run
+                     "gather_ceiling_gbs": probes["gather_gbs"] if probes else None,
+                     "frac_of_gather_ceiling": (probes["gather_ms"] / ms) if probes else None,
+                     "stream_read_gbs": probes["stream_read_gbs"] if probes else None,
                      "bytes_per_pair": bpp, "bytes_per_read": bpr,
                      "kernel": "filter_batched_kernel (+ worklist_kernel, in the same timing)"},
         "eager_ms_per_step": eager_ms,
+        "probes": probes,
         "plain_kernel": plain,
         "seed_location_checker": checker,
         "seeding": seeding,

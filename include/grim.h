@@ -286,6 +286,28 @@ int grim_window_order_workspace_size(const grim_index_t *idx, uint64_t n_reads, 
 int grim_window_order(const grim_index_t *idx, const uint32_t *win_lo, uint64_t n_reads,
                       uint32_t *order, void *workspace, uint64_t workspace_bytes, void *stream);
 
+/* ------------------------------------------------------------------- probes */
+/* Diagnostics: the memory ceilings the filter's rate is compared with.  The
+ * filter is bound by memory bandwidth (Section "Candidacy for 3D-Stacked Memory
+ * Implementations"); these calls measure what the device's memory delivers
+ * for the filter's own accesses, without its token work.
+ *
+ * grim_probe_gather: for every i < n, reads the bin vector of bin ids[i] from
+ * the index with the batched filter's gather (ids loaded coalesced, groups of
+ * lanes issuing 16-byte loads, several vectors in flight per group) and writes
+ * out[i] = its popcount, or -1 for an id >= n_bins (nothing is read then).
+ * ids (u32[n]) and out (int32[n]) are device memory.
+ *
+ * grim_probe_stream: reads the whole index once with 16-byte loads; *sink
+ * (device u32) is written only in the unlikely case that keeps the reads from
+ * being optimised away.
+ *
+ * Both: GRIM_E_INVALID for a NULL index or pointer, or when the current device
+ * is not the index's; asynchronous on `stream`; allocate nothing. */
+int grim_probe_gather(const grim_index_t *idx, const uint32_t *ids, uint64_t n, int32_t *out,
+                      void *stream);
+int grim_probe_stream(const grim_index_t *idx, uint32_t *sink, void *stream);
+
 /* ------------------------------------------------------------------- seeding */
 /* The step before the filter: the mapper looks up exact seeds of each read in a
  * hash table of reference locations and sends the locations to GRIM-Filter

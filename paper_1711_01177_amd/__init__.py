@@ -139,6 +139,8 @@ _SIGS = {
     "grim_index_transpose": (ctypes.c_int, [_vp, _vp]),
     "grim_filter_windows": (ctypes.c_int, [_vp, _P(grim_batch_t), _vp, _vp, _vp, _vp, _vp, _u64,
                                            _vp]),
+    "grim_probe_gather": (ctypes.c_int, [_vp, _vp, _u64, _vp, _vp]),
+    "grim_probe_stream": (ctypes.c_int, [_vp, _vp, _vp]),
     "grim_window_order_workspace_size": (ctypes.c_int, [_vp, _u64, _P(_u64)]),
     "grim_window_order": (ctypes.c_int, [_vp, _vp, _u64, _vp, _vp, _u64, _vp]),
     "grim_seed_index_build": (ctypes.c_int, [_vp, _u64, _u32, _P(_vp), _vp]),
@@ -508,6 +510,19 @@ def grim_window_order(index, win_lo, order=None, workspace=None, stream=None):
     _check(_lib.grim_window_order(index.handle, _ptr(win_lo), n, _ptr(order), _ptr(workspace),
                                   workspace.numel(), _stream(stream)), "grim_window_order")
     return order
+
+
+def grim_probe_gather(index, ids, out, n=None, stream=None):
+    """Gather probe: out[i] = popcount of bin ids[i]'s vector (-1 if out of
+    range), read with the batched filter's access pattern (device tensors)."""
+    n = int(ids.numel()) if n is None else int(n)
+    _check(_lib.grim_probe_gather(index.handle, _ptr(ids), n, _ptr(out), _stream(stream)),
+           "grim_probe_gather")
+
+
+def grim_probe_stream(index, sink, stream=None):
+    """Streaming-read probe over the whole index (sink: device int32 tensor)."""
+    _check(_lib.grim_probe_stream(index.handle, _ptr(sink), _stream(stream)), "grim_probe_stream")
 
 
 class SeedIndex:

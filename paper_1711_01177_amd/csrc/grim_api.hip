@@ -919,6 +919,42 @@ extern "C" int grim_window_order(const grim_index_t *idx, const uint32_t *win_lo
     return GRIM_E_UNSUPPORTED;
 }
 
+// ---------------------------------------------------------------- probes
+extern "C" int grim_probe_gather(const grim_index_t *idx, const uint32_t *ids, uint64_t n,
+                                 int32_t *out, void *stream)
+{
+    if (!idx || (n && (!ids || !out)))
+        return GRIM_E_INVALID;
+    if (n == 0)
+        return GRIM_OK;
+    int dev = -1;
+    int rc = current_device(&dev);
+    if (rc)
+        return rc;
+    if (dev != idx->device)
+        return GRIM_E_INVALID;
+    HIP_TRY(launch_probe_gather(reinterpret_cast<hipStream_t>(stream), idx->q,
+                                (uint32_t)cu_count(idx->device) * 8, idx->d_vec, idx->n_bins, ids,
+                                n, out));
+    return GRIM_OK;
+}
+
+extern "C" int grim_probe_stream(const grim_index_t *idx, uint32_t *sink, void *stream)
+{
+    if (!idx || !sink)
+        return GRIM_E_INVALID;
+    int dev = -1;
+    int rc = current_device(&dev);
+    if (rc)
+        return rc;
+    if (dev != idx->device)
+        return GRIM_E_INVALID;
+    HIP_TRY(launch_probe_stream(reinterpret_cast<hipStream_t>(stream),
+                                (uint32_t)cu_count(idx->device) * 8, idx->d_vec, idx->bytes / 16,
+                                sink));
+    return GRIM_OK;
+}
+
 // ---------------------------------------------------------------- graphs
 struct grim_graph {
     hipGraph_t graph;

@@ -105,6 +105,13 @@ hipError_t launch_transpose(hipStream_t s, int q, const uint32_t *vec, uint64_t 
 // Persistent grid: as many workgroups as fit on the device's cus compute units
 // at once (at most one per read).
 hipError_t launch_window(hipStream_t s, int q, uint32_t cus, size_t lds, const WindowArgs &a);
+
+// Memory-ceiling probes (grim_probe.hip): the batched filter's gather of bin
+// vectors without its token work, and a streaming read.
+hipError_t launch_probe_gather(hipStream_t s, uint32_t q, uint32_t grid, const void *vec,
+                               uint64_t n_records, const uint32_t *ids, uint64_t n, int32_t *out);
+hipError_t launch_probe_stream(hipStream_t s, uint32_t grid, const void *src, uint64_t n16,
+                               uint32_t *sink);
 hipError_t launch_filter(const void *kernel, dim3 grid, dim3 block, size_t lds_bytes,
                          hipStream_t s, const FilterArgs &a);
 
