@@ -6,10 +6,11 @@
 // together).
 //
 // Token-major copy of the index: row t holds bit b = "token t occurs in bin b"
-// for every bin (ceil(n_bins / 64) * 2 words per row).  For a (read, window)
-// each thread owns 32 consecutive bins (one word of every row) and adds, for
-// every token position of the read, that token's row word into bit-sliced
-// counters (ripple-carry over planes), so repeated tokens count once per
+// for every bin (ceil(n_bins / 64) * 2 words per row, plus one pad word at the
+// end of the buffer).  For a (read, window) each thread owns 32 consecutive
+// bins of the window (two adjacent row words joined by a funnel shift) and
+// adds, for every token position of the read, that token's bits into a
+// bit-sliced counter (carry-save adders), so repeated tokens count once per
 // position.  Each token costs one coalesced row segment for the whole window.
 #include <hip/hip_runtime.h>
 
