@@ -1,5 +1,6 @@
 // Seed Location Checker kernels for gfx950: compaction of the seed location
-// filter bitmask into the list of surviving locations.
+// filter bitmask into the list of surviving locations, and the alignment check
+// of the survivors (edit distance of the read within its bin's span).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
