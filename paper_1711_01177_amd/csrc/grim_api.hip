@@ -524,12 +524,14 @@ extern "C" int grim_default_tuning(uint32_t q, grim_tuning_t *out)
 {
     if (!out)
         return GRIM_E_INVALID;
+    // the shapes the autotuner picks on the 3.1 Gbp workloads (q = 5: 8.3e8
+    // pairs, q = 6: 2.0e9 pairs); q = 4 and 7 from the parity sweeps
     grim_tuning_t t = {0, 0, 1024, 8};
     switch (q) {
-    case 4: t.lanes_per_cand = 2; t.unroll = 8; break;
-    case 5: t.lanes_per_cand = 4; t.unroll = 4; break;
-    case 6: t.lanes_per_cand = 32; t.unroll = 4; break;
-    case 7: t.lanes_per_cand = 64; t.unroll = 2; break;
+    case 4: t = {2, 8, 1024, 8}; break;
+    case 5: t = {4, 4, 1024, 4}; break;
+    case 6: t = {8, 2, 512, 4}; break;
+    case 7: t = {64, 2, 1024, 8}; break;
     default: return GRIM_E_UNSUPPORTED;
     }
     *out = t;
