@@ -331,7 +331,7 @@ __global__ __launch_bounds__(256) void verify_kernel(VerifyArgs a)
                     peq[(3 * W + w) * 256 + t] = pt;
                 }
                 const int wu = (int)((L + 63) >> 6);
-                const uint64_t hb = 1ull << ((L - 1) & 63);
+                const uint32_t last_bit = (L - 1) & 63;    // the read's last row in its last block
                 const uint64_t lo = (uint64_t)b * a.B;
                 uint64_t hi = lo + a.B + a.O;
                 if (hi > a.G)
@@ -351,29 +351,30 @@ __global__ __launch_bounds__(256) void verify_kernel(VerifyArgs a)
 #pragma unroll
                     for (int w = 0; w < W; ++w)
                         eqw[w] = pq[w * 256];
-                    int h = 0;
+                    // horizontal delta leaving a block's bottom row: +1 (hp = 1),
+                    // -1 (hm = 1) or 0, carried into the next block as 0/1 words;
+                    // the boundary row above block 0 contributes 0
+                    uint64_t hp = 0, hm = 0;
 #pragma unroll
                     for (int w = 0; w < W; ++w) {
                         if (w < wu) {
-                            // carry-in from the block above as two 0/1 words
-                            // (h is -1, 0 or +1), so no lane branches on it
-                            const uint64_t hm_in = (uint64_t)(h < 0), hp_in = (uint64_t)(h > 0);
                             uint64_t eq = eqw[w];
                             const uint64_t xv = eq | Mv[w];
-                            eq |= hm_in;
+                            eq |= hm;
                             const uint64_t xh = (((eq & Pv[w]) + Pv[w]) ^ Pv[w]) | eq;
                             uint64_t ph = Mv[w] | ~(xh | Pv[w]);
                             uint64_t mh = Pv[w] & xh;
-                            const uint64_t top = (w == wu - 1) ? hb : (1ull << 63);
-                            const int hout = (ph & top) ? 1 : ((mh & top) ? -1 : 0);
-                            ph = (ph << 1) | hp_in;
-                            mh = (mh << 1) | hm_in;
+                            const uint32_t tb = (w == wu - 1) ? last_bit : 63u;
+                            const uint64_t hp_out = (ph >> tb) & 1ull, hm_out = (mh >> tb) & 1ull;
+                            ph = (ph << 1) | hp;
+                            mh = (mh << 1) | hm;
                             Pv[w] = mh | ~(xv | ph);
                             Mv[w] = ph & xv;
-                            h = hout;
+                            hp = hp_out;
+                            hm = hm_out;
                         }
                     }
-                    score += h;
+                    score += (int32_t)hp - (int32_t)hm;
                     best = min(best, score);
                 }
                 d = min<int32_t>(best, (int32_t)E + 1);
