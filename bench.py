@@ -211,6 +211,76 @@ def serving_leg(g, idx, w, rng, loads=(0.25, 0.5, 0.75, 0.9), n_requests=10_000,
     return out
 
 
+def seeding_leg(g, torch, stream):
+    """The step before the filter, on the mid recipe (100 Mbp reference with 10 %
+    repeats, 1M reads of 100 bp, exact 12-mer seeds at read offsets 0, 12, ...,
+    200-bp bins, <= 4096 bins per read): k-mer index and candidate lists on the
+    GPU, then the filter and the survivor list on those candidates.  Reports
+    the share of reads whose true bin is among their candidates."""
+    import grim_synth as gs
+    t0 = time.time()
+    wm = gs.WORKLOADS["mid"]
+    ref = gs.make_reference("mid")
+    rd = gs.reads(gs.SEEDS["reads"], ref, wm["n_reads"], wm["lengths"], wm["e_nums"], gs.E_DEN)
+    n = int(rd["read_len"].size)
+    rb = g.Batch(rd["codes"], rd["read_off"], rd["read_len"], rd["read_e"], gs.E_DEN,
+                 np.zeros(n + 1, np.uint64), np.zeros(0, np.uint32), max_len=int(wm["lengths"][0]))
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    si = g.SeedIndex(ref, 12)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    build_ms = e0.elapsed_time(e1)
+    cands = g.grim_seed_candidates(si, rb, wm["B"], 4096)
+    e0.record(stream)
+    for _ in range(3):
+        g.grim_seed_candidates(si, rb, wm["B"], 4096).free()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    cand_ms = e0.elapsed_time(e1) / 3
+    off, bins = cands.to_host()
+    # true bin among the read's candidates: pairs keyed (read, bin) are sorted
+    tb = (rd["read_z"] // wm["B"]).astype(np.int64)
+    reads_of = np.repeat(np.arange(n, dtype=np.int64), np.diff(off.astype(np.int64)))
+    keys = (reads_of << 32) | bins.astype(np.int64)
+    want = (np.arange(n, dtype=np.int64) << 32) | tb
+    at = np.minimum(np.searchsorted(keys, want), max(0, keys.size - 1))
+    found = int(np.count_nonzero(keys[at] == want)) if keys.size else 0
+    del reads_of, keys, want, at
+    # the filter and the checker on the seeded candidates
+    idx = g.grim_build_bins(ref, wm["q"], wm["B"], wm["O"])
+    fb = g.batch_with_candidates(rb, cands)
+    np_ = fb.n_pairs
+    c, bb = g.alloc_outputs(np_)
+    ws = g.alloc_workspace(idx, np_)
+    g.grim_filter_batch(idx, fb, c, bb, ws)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(5):
+        g.grim_filter_batch(idx, fb, c, bb, ws)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    filt_ms = e0.elapsed_time(e1) / 5
+    rc, _ = g.grim_filter_status(ws)
+    sp, sr, sb, total = g.grim_compact_survivors(fb, bb)
+    out = dict(recipe="mid: 100 Mbp, 10 % repeats, 1M x 100 bp, exact 12-mer seeds, 200-bp bins",
+               index_build_ms=build_ms, candidates_ms=cand_ms,
+               reads_per_s=n / (cand_ms * 1e-3), pairs=int(np_),
+               true_bin_found=found / n, filter_ms=filt_ms, filter_status=rc,
+               survivors=int(total),
+               note="seeding calls are synchronous and include the library's temporary "
+                    "allocations; the candidate lists equal the host generator's (bench.py "
+                    "--config mid, tests/test_gpu_seed.py)")
+    log(f"[bench] seeding (mid recipe): index {build_ms:.1f} ms, candidates {cand_ms:.2f} ms for "
+        f"{n} reads -> {np_} pairs, true bin found for {100 * found / n:.2f} % of reads; filter "
+        f"{filt_ms:.3f} ms, {total} survivors ({time.time() - t0:.1f}s)")
+    del sp, sr, sb, c, bb, ws, fb
+    cands.free()
+    si.free()
+    idx.free()
+    return out
+
+
 def window_leg(g, idx, w, torch, stream, rng, window_bins=4096, n_reads=200_000):
     """The bin-window form: each of n_reads reads against the window_bins
     consecutive bins around its true bin, from the token-major index copy.
@@ -323,6 +393,8 @@ def main():
     ap.add_argument("--wg", type=int, default=0)
     ap.add_argument("--cpu-pairs", type=float, default=3.0e8)
     ap.add_argument("--no-window", action="store_true", help="skip the bin-window leg")
+    ap.add_argument("--no-seed", action="store_true",
+                    help="skip the GPU seeding leg (mid recipe) of the default workload")
     ap.add_argument("--no-probe", action="store_true",
                     help="skip the memory-ceiling probes (gather and streaming read)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
@@ -562,6 +634,9 @@ def main():
         log(f"[bench] alignment check: {n_ok}/{total} survivors within E edits, {vms:.3f} ms")
         del dist, okb
     del sp, sr, sb
+
+    if args.config == "batched" and not args.no_seed:
+        seeding = seeding_leg(g, torch, stream)
 
     window = None
     if args.config == "batched" and not args.no_window:
