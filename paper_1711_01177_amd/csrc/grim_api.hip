@@ -351,12 +351,18 @@ extern "C" int grim_build_bins(const uint32_t *ref_2bit, uint64_t ref_len, const
     }
     hipError_t e = hipMemcpyAsync(d_ref, ref_2bit, nw * 4, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) {
-        uint64_t grid = (n_bins + 3) / 4;
-        const uint64_t cap = (uint64_t)cu_count(dev) * 32;
-        if (grid > cap)
-            grid = cap;
-        e = launch_build(p->q, dim3((uint32_t)grid), s, d_ref, nw, ref_len, p->bin_stride,
-                         p->overlap, n_bins, reinterpret_cast<uint32_t *>(idx->d_vec));
+        uint32_t *vec = reinterpret_cast<uint32_t *>(idx->d_vec);
+        e = launch_build_chunked(p->q, (uint32_t)cu_count(dev), s, d_ref, nw, ref_len,
+                                 p->bin_stride, p->overlap, n_bins, vec);
+        if (e == hipErrorNotSupported) {
+            (void)hipGetLastError();
+            uint64_t grid = (n_bins + 3) / 4;
+            const uint64_t cap = (uint64_t)cu_count(dev) * 32;
+            if (grid > cap)
+                grid = cap;
+            e = launch_build(p->q, dim3((uint32_t)grid), s, d_ref, nw, ref_len, p->bin_stride,
+                             p->overlap, n_bins, vec);
+        }
     }
     if (e == hipSuccess)
         e = hipStreamSynchronize(s);

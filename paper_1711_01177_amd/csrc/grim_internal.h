@@ -90,6 +90,9 @@ const void *plain_kernel(int q);
 
 hipError_t launch_build(int q, dim3 grid, hipStream_t s, const uint32_t *ref, uint64_t nw,
                         uint64_t G, uint64_t B, uint64_t O, uint64_t n_bins, uint32_t *out);
+hipError_t launch_build_chunked(int q, uint32_t cus, hipStream_t s, const uint32_t *ref,
+                                uint64_t nw, uint64_t G, uint64_t B, uint64_t O, uint64_t n_bins,
+                                uint32_t *out);
 hipError_t launch_worklist(hipStream_t s, const uint64_t *cand_off, uint64_t n_reads,
                            uint32_t tile_pairs, uint32_t n_tiles, uint32_t *tile_read,
                            uint32_t *status, uint32_t *counter);
