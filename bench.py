@@ -105,9 +105,47 @@ def cpu_baseline(w, target_pairs, n_threads, idx=None):
                 pairs_per_s=n_pairs / dt), (c, p), idx
 
 
+def link_probe(torch, n_bytes=256 << 20, reps=5):
+    """Host link rates (GB/s) with page-locked buffers: one direction at a
+    time, then both at once on two streams (best of reps)."""
+    h = torch.empty(n_bytes, dtype=torch.uint8, pin_memory=True)
+    h2 = torch.empty(n_bytes, dtype=torch.uint8, pin_memory=True)
+    d = torch.empty(n_bytes, dtype=torch.uint8, device="cuda")
+    d2 = torch.empty(n_bytes, dtype=torch.uint8, device="cuda")
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+
+    def best(fn):
+        fn()
+        t = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            t.append(time.perf_counter() - t0)
+        return n_bytes / min(t) / 1e9
+
+    def up():
+        with torch.cuda.stream(s1):
+            d.copy_(h, non_blocking=True)
+
+    def down():
+        with torch.cuda.stream(s1):
+            h.copy_(d, non_blocking=True)
+
+    def both():
+        up()
+        with torch.cuda.stream(s2):
+            h2.copy_(d2, non_blocking=True)
+
+    out = dict(h2d_gbs=best(up), d2h_gbs=best(down), both_each_gbs=best(both))
+    del h, h2, d, d2
+    return out
+
+
 def serving_leg(g, idx, w, rng, loads=(0.25, 0.5, 0.75, 0.9), n_requests=10_000, pool=256,
-                max_reads=65536, inplace=True, tick_pairs=64 << 20, n_streams=3,
-                fixed_rates=None):
+                max_reads=65536, inplace=True, tick_pairs=8 << 20, n_streams=3,
+                max_inflight=1024, fixed_rates=None):
     """Served latency.  A pool of `pool` requests of log-uniform size
     (1..max_reads reads) is cut from the workload.  First the server's capacity
     is measured closed-loop (a burst of requests submitted at once); then, for
@@ -117,8 +155,8 @@ def serving_leg(g, idx, w, rng, loads=(0.25, 0.5, 0.75, 0.9), n_requests=10_000,
     is recorded.  inplace=True submits pinned request buffers without copying
     (results land in the request's pinned output buffers, so a buffer is in
     flight at most once at a time); False uses the copying submission.  Ticks
-    hold at most tick_pairs pairs, so larger requests run in parts whose copies
-    and launches overlap on n_streams streams.  fixed_rates (pairs per second)
+    hold at most tick_pairs pairs, so larger requests run in parts; n_streams
+    ticks (and at most max_inflight requests) are in flight at once.  fixed_rates (pairs per second)
     replaces the loads relative to capacity by absolute arrival rates, so that
     server configurations can be compared at the same offered traffic."""
     n_reads = w["read_len"].size
@@ -134,7 +172,7 @@ def serving_leg(g, idx, w, rng, loads=(0.25, 0.5, 0.75, 0.9), n_requests=10_000,
                                 w["read_e"][r0:r1], w["e_den"], w["cand_off"][r0:r1 + 1] - c0,
                                 w["cand_bin"][c0:c1], max_len=250, pinned=inplace))
     mean_pairs = float(np.mean([hb.n_pairs for hb in reqs]))
-    srv = g.Server(idx, hbm_budget_bytes=4 << 30, max_inflight=64, n_streams=n_streams,
+    srv = g.Server(idx, hbm_budget_bytes=4 << 30, max_inflight=max_inflight, n_streams=n_streams,
                    max_tick_pairs=tick_pairs, max_len=256)
     submit = srv.submit_inplace if inplace else srv.submit
 
@@ -157,12 +195,20 @@ def serving_leg(g, idx, w, rng, loads=(0.25, 0.5, 0.75, 0.9), n_requests=10_000,
         drain([submit(hb) for hb in reqs])
         walls.append(time.perf_counter() - t0)
     capacity = sum(hb.n_pairs for hb in reqs) / float(np.mean(walls))
-    srv.stats(reset=True)
+    cap_stats = srv.stats(reset=True)
+    # bytes each request moves over the host link: inputs one way, counts and
+    # pass bits (the tick's bits via the stage, then ORed in) back
+    n_pairs_all = sum(hb.n_pairs for hb in reqs)
+    up_bytes = sum(hb.words.size * 4 + hb.n_reads * 24 + 8 + hb.n_pairs * 4 for hb in reqs)
+    down_bytes = sum(hb.n_pairs * 4 + ((hb.n_pairs + 31) // 32) * 4 for hb in reqs)
     out = dict(mode="in place, pinned buffers" if inplace else "copying submission",
                pool_requests=pool, mean_pairs_per_request=mean_pairs,
-               max_tick_pairs=tick_pairs, n_streams=n_streams,
+               max_tick_pairs=tick_pairs, n_streams=n_streams, max_inflight=max_inflight,
                capacity_burst_s=walls,
-               capacity_pairs_per_s=capacity, points=[])
+               capacity_pairs_per_s=capacity,
+               capacity_ticks=cap_stats["ticks"],
+               link_bytes_per_pair=dict(up=up_bytes / n_pairs_all, down=down_bytes / n_pairs_all),
+               points=[])
     points = [(rho, rho * capacity) for rho in loads] if fixed_rates is None else \
         [(r / capacity, r) for r in fixed_rates]
     for rho, pair_rate in points:
@@ -203,6 +249,7 @@ def serving_leg(g, idx, w, rng, loads=(0.25, 0.5, 0.75, 0.9), n_requests=10_000,
                                   mean_ms=st["mean_ms"], max_ms=st["max_ms"],
                                   pairs_per_s=st["pairs_done"] / wall,
                                   mean_requests_per_tick=st["mean_requests_per_tick"],
+                                  ticks=st["ticks"],
                                   arrivals_delayed_by_full_pool=late))
     srv.destroy()
     mid = next(p for p in out["points"] if p["offered_load"] == 0.5) \
@@ -654,7 +701,16 @@ def main():
     if not args.no_serve:
         try:
             t0 = time.time()
+            link = link_probe(torch)
             serving = serving_leg(g, idx, w, rng, n_requests=args.serve_requests, inplace=True)
+            # the link ceiling: both directions at once, the busier one decides
+            bpp = serving["link_bytes_per_pair"]
+            ceiling = link["both_each_gbs"] * 1e9 / max(bpp["up"], bpp["down"])
+            serving["link"] = dict(link, ceiling_pairs_per_s=ceiling,
+                                   capacity_frac_of_ceiling=serving["capacity_pairs_per_s"] / ceiling)
+            log(f"[bench] host link: {link['h2d_gbs']:.1f} GB/s up, {link['d2h_gbs']:.1f} down, "
+                f"{link['both_each_gbs']:.1f} each way at once -> serving ceiling {ceiling:.3e} "
+                f"pairs/s ({bpp['up']:.2f} B up, {bpp['down']:.2f} B down per pair)")
             serving["copying_submission"] = serving_leg(g, idx, w, rng, loads=(0.5,),
                                                         n_requests=args.serve_requests,
                                                         inplace=False)
@@ -662,7 +718,8 @@ def main():
                 log(f"[bench] serving at {pt['offered_load']:.2f} x capacity "
                     f"({pt['offered_rps']:.0f} req/s): p50 {pt['p50_ms']:.2f} ms "
                     f"p99 {pt['p99_ms']:.2f} ms, {pt['pairs_per_s']:.3e} pairs/s")
-            log(f"[bench] serving capacity {serving['capacity_pairs_per_s']:.3e} pairs/s in place, "
+            log(f"[bench] serving capacity {serving['capacity_pairs_per_s']:.3e} pairs/s in place "
+                f"({100 * serving['link']['capacity_frac_of_ceiling']:.0f} % of the link ceiling), "
                 f"{serving['copying_submission']['capacity_pairs_per_s']:.3e} copying "
                 f"({time.time() - t0:.1f}s)")
         except Exception as ex:  # report, keep the throughput line

@@ -371,10 +371,10 @@ typedef struct grim_server grim_server_t;
 
 typedef struct grim_serve_cfg {
     uint64_t hbm_budget_bytes;  /* device bytes for request buffers (0 = 1 GiB)     */
-    uint32_t max_inflight;      /* requests on the device at once (0 = 64)          */
-    uint32_t n_streams;         /* concurrent ticks (0 = 2)                         */
+    uint32_t max_inflight;      /* requests on the device at once (0 = 1024)        */
+    uint32_t n_streams;         /* concurrent ticks (0 = 3)                         */
     uint32_t max_tick_pairs;    /* pairs per launch; larger requests run in parts
-                                   of whole reads (0 = 64M)                         */
+                                   of whole reads (0 = 8M)                          */
     uint32_t max_len;           /* longest read accepted (0 = 1024)                 */
 } grim_serve_cfg_t;
 

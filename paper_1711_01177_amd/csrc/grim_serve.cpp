@@ -772,11 +772,11 @@ extern "C" int grim_serve_create(const grim_index_t *idx, const grim_serve_cfg_t
     if (!c.hbm_budget_bytes)
         c.hbm_budget_bytes = 1ull << 30;
     if (!c.max_inflight)
-        c.max_inflight = 64;
+        c.max_inflight = 1024;
     if (!c.n_streams)
-        c.n_streams = 2;
+        c.n_streams = 3;
     if (!c.max_tick_pairs)
-        c.max_tick_pairs = 64u << 20;
+        c.max_tick_pairs = 8u << 20;
     if (!c.max_len)
         c.max_len = 1024;
     if (c.max_len > grim::kMaxLen || c.n_streams > 16)

@@ -229,6 +229,35 @@ def test_inplace_submission_matches_alone(setup):
     srv.destroy()
 
 
+def test_pageable_inplace_submission(setup):
+    """In-place requests in pageable memory (staged by the runtime), alone and
+    in ticks mixed with pinned ones: every request equals its solo run and its
+    counts land in the caller's buffer."""
+    g, w, idx = setup
+    reqs = make_requests(g, w, 18, 19, max_reads=800)
+    solo = [alone(g, idx, sub) for sub, _ in reqs]
+    pageable = [g.HostBatch(sub["codes"], sub["read_off"], sub["read_len"], sub["read_e"],
+                            sub["e_den"], sub["cand_off"], sub["cand_bin"], max_len=256)
+                for sub, _ in reqs]
+    pinned = [g.HostBatch(sub["codes"], sub["read_off"], sub["read_len"], sub["read_e"],
+                          sub["e_den"], sub["cand_off"], sub["cand_bin"], max_len=256, pinned=True)
+              for sub, _ in reqs]
+    for name, batches in (("pageable", pageable), ("pinned", pinned),
+                          ("mixed", [pageable[i] if i % 2 else pinned[i] for i in range(len(reqs))])):
+        srv = g.Server(idx, hbm_budget_bytes=64 << 20, max_inflight=8, n_streams=2, max_len=256)
+        ts = [srv.submit_inplace(hb) for hb in batches]
+        for i, t in enumerate(ts):
+            rc, c, b, st = srv.wait(t)
+            assert rc == solo[i][0] == 0, (name, i, rc)
+            assert np.array_equal(c, solo[i][1]), f"{name}: request {i} counts"
+            assert np.array_equal(b, solo[i][2]), f"{name}: request {i} pass bits"
+            assert np.array_equal(batches[i].out_counts[:c.size], solo[i][1])
+        s = srv.stats()
+        say(name, s)
+        assert s["completed"] == len(reqs)
+        srv.destroy()
+
+
 def test_requests_split_into_parts(setup):
     """Requests with more pairs than max_tick_pairs run in parts of whole reads
     (at 100 pairs down to single reads with more candidates than the limit):
