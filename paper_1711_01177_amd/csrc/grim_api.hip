@@ -812,7 +812,8 @@ extern "C" int grim_index_transpose(grim_index_t *idx, void *stream)
 {
     if (!idx)
         return GRIM_E_INVALID;
-    const uint64_t row_words = ((idx->n_bins + 63) / 64) * 2;
+    // one 32-word (1024-bin) segment of every row per transpose tile
+    const uint64_t row_words = ((idx->n_bins + 1023) / 1024) * 32;
     const uint64_t n_rows = 1ull << (2 * idx->q);
     uint32_t *rows = nullptr;
     // one pad word past the last row: the window kernel reads two adjacent
@@ -820,9 +821,8 @@ extern "C" int grim_index_transpose(grim_index_t *idx, void *stream)
     if (hipMalloc(&rows, n_rows * row_words * 4 + 256) != hipSuccess)
         return GRIM_E_NOMEM;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    const uint64_t groups = (idx->n_bins + 63) / 64;
-    uint64_t grid = (groups + 3) / 4;
-    const uint64_t cap = (uint64_t)cu_count(idx->device) * 32;
+    uint64_t grid = row_words / 32;
+    const uint64_t cap = (uint64_t)cu_count(idx->device) * 2;
     if (grid > cap)
         grid = cap;
     hipError_t e = launch_transpose(s, idx->q, reinterpret_cast<const uint32_t *>(idx->d_vec),

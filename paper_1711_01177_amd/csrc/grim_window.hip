@@ -6,8 +6,8 @@
 // together).
 //
 // Token-major copy of the index: row t holds bit b = "token t occurs in bin b"
-// for every bin (ceil(n_bins / 64) * 2 words per row, plus one pad word at the
-// end of the buffer).  For a (read, window) each thread owns 32 consecutive
+// for every bin (ceil(n_bins / 1024) * 32 words per row, zero past the last
+// bin, plus one pad word at the end of the buffer).  For a (read, window) each thread owns 32 consecutive
 // bins of the window (two adjacent row words joined by a funnel shift) and
 // adds, for every token position of the read, that token's bits into a
 // bit-sliced counter (carry-save adders), so repeated tokens count once per
@@ -34,33 +34,86 @@ __device__ __forceinline__ uint32_t win_token_at(const uint32_t *__restrict__ w,
     return (uint32_t)((x << sh) >> (64 - 2 * Q));
 }
 
-// Transpose: one wavefront per group of 64 consecutive bins.  Lane j holds word
-// w of bin (64g + j)'s vector; the ballot of bit i over the lanes is the 64-bit
-// row segment of token 32w + i for those 64 bins.
+// Transpose of 32 x 32 bits held one row per lane in each half-wavefront: on
+// entry lane r holds x with bit c = M[r][c], on exit lane r holds bit c =
+// M[c][r].  Stage s exchanges x with lane r ^ s and swaps the two s x s
+// off-diagonal blocks of each 2s x 2s block (bit log2(s) of the row index
+// trades places with bit log2(s) of the column index; the five stages commute).
+__device__ __forceinline__ uint32_t transpose32(uint32_t x, uint32_t lane)
+{
+#define GRIM_T32_STAGE(S, M)                                                                      \
+    {                                                                                            \
+        const uint32_t xp = (uint32_t)__builtin_amdgcn_ds_swizzle((int)x, 0x1F | ((S) << 10));   \
+        const bool upper = (lane & (S)) != 0;                                                    \
+        const uint32_t lo = upper ? xp : x, hi = upper ? x : xp;                                 \
+        const uint32_t t = ((lo >> (S)) ^ hi) & (M);                                             \
+        x ^= upper ? t : (t << (S));                                                             \
+    }
+    GRIM_T32_STAGE(16, 0x0000FFFFu)
+    GRIM_T32_STAGE(8, 0x00FF00FFu)
+    GRIM_T32_STAGE(4, 0x0F0F0F0Fu)
+    GRIM_T32_STAGE(2, 0x33333333u)
+    GRIM_T32_STAGE(1, 0x55555555u)
+#undef GRIM_T32_STAGE
+    return x;
+}
+
+// Transpose: a workgroup of 16 wavefronts takes 1024 consecutive bins (16
+// groups of 64, one per wavefront, lane = bin).  Each lane loads 128 bytes of
+// its bin's vector at a time (32 words: tokens 1024c .. 1024c + 1023) and
+// bit-transposes each word with its half-wavefront, so lane i of half h holds
+// token (32w + i)'s bits for bins 32h .. 32h + 31 of its group.  Four words
+// (128 rows) at a time are staged in LDS and written out as whole 128-byte row
+// segments of the tile (row_words is a multiple of 32: every tile owns one
+// aligned 32-word segment of every row; bins past the last one are zero).
+constexpr int kTrThreads = 1024;
+constexpr int kTrRowPad = 33;  // LDS row stride (words): lanes of one word hit different banks
+
 template <int Q>
-__global__ __launch_bounds__(256) void transpose_kernel(const uint32_t *__restrict__ vec,
-                                                        uint64_t n_bins, uint64_t row_words,
-                                                        uint32_t *__restrict__ rows)
+__global__ __launch_bounds__(kTrThreads) void transpose_kernel(const uint32_t *__restrict__ vec,
+                                                               uint64_t n_bins, uint64_t row_words,
+                                                               uint32_t *__restrict__ rows)
 {
     constexpr int VW = (1 << (2 * Q)) >> 5;
-    const int lane = threadIdx.x & 63;
-    const uint64_t n_groups = (n_bins + 63) / 64;
-    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
-    for (uint64_t gidx = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-         gidx < n_groups; gidx += waves) {
-        const uint64_t b = gidx * 64 + lane;
-        for (int w = 0; w < VW; ++w) {
-            const uint32_t x = b < n_bins ? vec[b * VW + w] : 0u;
-#pragma unroll 8
-            for (int i = 0; i < 32; ++i) {
-                const uint64_t m = __ballot((x >> i) & 1u);
-                if (lane == 0) {
-                    uint32_t *dst = rows + (uint64_t)(32 * w + i) * row_words + gidx * 2;
-                    dst[0] = (uint32_t)m;
-                    dst[1] = (uint32_t)(m >> 32);
+    constexpr int CW = VW < 32 ? VW : 32;  // words per load pass
+    __shared__ uint32_t stage[128 * kTrRowPad];
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const uint32_t half = lane >> 5, li = lane & 31;
+    const uint64_t n_tiles = row_words / 32;
+    for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        const uint64_t b = (tile * 16 + wv) * 64 + lane;
+        const uint4 *src = reinterpret_cast<const uint4 *>(vec + b * VW);
+        for (int c = 0; c < VW / CW; ++c) {
+            uint32_t x[CW];
+#pragma unroll
+            for (int k = 0; k < CW / 4; ++k) {
+                const uint4 v = b < n_bins ? src[c * (CW / 4) + k] : make_uint4(0u, 0u, 0u, 0u);
+                x[4 * k] = v.x;
+                x[4 * k + 1] = v.y;
+                x[4 * k + 2] = v.z;
+                x[4 * k + 3] = v.w;
+            }
+#pragma unroll
+            for (int st = 0; st < CW / 4; ++st) {
+                uint32_t y[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    y[u] = transpose32(x[4 * st + u], li);
+                __syncthreads();  // the previous step's rows have been written out
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    stage[(32 * u + li) * kTrRowPad + 2 * wv + half] = y[u];
+                __syncthreads();
+                const uint64_t r0 = (uint64_t)(c * CW + 4 * st) * 32;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const uint32_t idx = tid + j * kTrThreads;  // 128 rows x 32 words
+                    const uint32_t rl = idx >> 5, ww = idx & 31;
+                    rows[(r0 + rl) * row_words + tile * 32 + ww] = stage[rl * kTrRowPad + ww];
                 }
             }
         }
+        __syncthreads();  // stage reused by the next tile
     }
 }
 
@@ -362,11 +415,14 @@ __global__ __launch_bounds__(256) void window_kernel(WindowArgs a)
 hipError_t launch_transpose(hipStream_t s, int q, const uint32_t *vec, uint64_t n_bins,
                             uint64_t row_words, uint32_t *rows, uint32_t grid)
 {
+    if (row_words % 32 != 0 || row_words * 32 < n_bins)
+        return hipErrorInvalidValue;
+    const dim3 blk(kTrThreads);
     switch (q) {
-    case 4: hipLaunchKernelGGL(transpose_kernel<4>, dim3(grid), dim3(256), 0, s, vec, n_bins, row_words, rows); break;
-    case 5: hipLaunchKernelGGL(transpose_kernel<5>, dim3(grid), dim3(256), 0, s, vec, n_bins, row_words, rows); break;
-    case 6: hipLaunchKernelGGL(transpose_kernel<6>, dim3(grid), dim3(256), 0, s, vec, n_bins, row_words, rows); break;
-    case 7: hipLaunchKernelGGL(transpose_kernel<7>, dim3(grid), dim3(256), 0, s, vec, n_bins, row_words, rows); break;
+    case 4: hipLaunchKernelGGL(transpose_kernel<4>, dim3(grid), blk, 0, s, vec, n_bins, row_words, rows); break;
+    case 5: hipLaunchKernelGGL(transpose_kernel<5>, dim3(grid), blk, 0, s, vec, n_bins, row_words, rows); break;
+    case 6: hipLaunchKernelGGL(transpose_kernel<6>, dim3(grid), blk, 0, s, vec, n_bins, row_words, rows); break;
+    case 7: hipLaunchKernelGGL(transpose_kernel<7>, dim3(grid), blk, 0, s, vec, n_bins, row_words, rows); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -78,23 +78,34 @@ def test_windows_long_reads_and_empty():
     assert e.value.code == g.GRIM_E_UNSUPPORTED
 
 
-def test_transpose_layout():
-    """Row t, bit b of the token-major copy = bit t of bin b's vector."""
-    import torch
+@pytest.mark.parametrize("q,G,B", [(4, 250_000, 97), (5, 250_000, 97), (6, 250_000, 200),
+                                   (7, 60_001, 50)])
+def test_transpose_layout(q, G, B):
+    """Row t, bit b of the token-major copy = bit t of bin b's vector: a window
+    over every bin for a read that is just token t, for every token (q <= 5) or
+    tokens sampled across every 1024-token load pass (q = 6, 7); bin counts span
+    several 1024-bin transpose tiles with a ragged last one."""
     g = lib()
-    ref = gs.reference(51, 50_000)
-    idx = g.grim_build_bins(ref, 4, 97, 30)
+    ref = gs.reference(51 + q, G)
+    idx = g.grim_build_bins(ref, q, B, 30)
     idx.transpose()
-    vec = idx.to_host()                                   # (n_bins, 32) bytes for q=4
-    bits = np.unpackbits(vec, axis=1, bitorder="little")  # (n_bins, 256)
-    # read rows back through a window call on a single read would be indirect;
-    # instead compare a window filter of the all-token read with popcounts
+    vec = idx.to_host()
+    bits = np.unpackbits(vec, axis=1, bitorder="little")  # (n_bins, 4^q)
     nb = idx.n_bins
-    reads = [np.array([(t >> 6) & 3, (t >> 4) & 3, (t >> 2) & 3, t & 3], np.uint8) for t in range(256)]
-    w = window_workload(ref, 4, 97, 30, reads, [0] * 256, [0] * 256, [nb] * 256)
-    out = run_windows(g, idx, w, [0] * 256)
-    got = out[0].reshape(256, nb)
-    assert np.array_equal(got, bits.T.astype(np.int32))
+    n_tok = 4 ** q
+    if q <= 5:
+        toks = np.arange(n_tok)
+    else:
+        rng = np.random.default_rng(q)
+        edges = [0, 31, 32, 127, 128, 1023, 1024, n_tok - 1]
+        toks = np.unique(np.concatenate([edges, rng.integers(0, n_tok, 300)]))
+    reads = [np.array([(int(t) >> (2 * (q - 1 - j))) & 3 for j in range(q)], np.uint8)
+             for t in toks]
+    k = len(toks)
+    w = window_workload(ref, q, B, 30, reads, [0] * k, [0] * k, [nb] * k)
+    out = run_windows(g, idx, w, [0] * k)
+    got = out[0].reshape(k, nb)
+    assert np.array_equal(got, bits[:, toks].T.astype(np.int32))
 
 
 def test_windows_token_blocks_and_many_reads():
