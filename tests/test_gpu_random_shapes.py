@@ -98,3 +98,37 @@ def test_random_shape(seed):
         okb = ok.cpu().numpy().view(np.uint32)
         okn = (okb[np.arange(total) >> 5] >> (np.arange(total) & 31)) & 1
         assert np.array_equal(okn.astype(bool), want <= E[srn])
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_random_shape_windows_and_seeding(seed):
+    """The same cases through the bin-window form (a random window of 1-300
+    consecutive bins per read, some running past the last bin) and through
+    device seeding (k = 4-12, caps from 1 to 4096), against the oracle."""
+    from tests.test_gpu_window import run_windows, window_workload
+    g = lib()
+    w = make_case(seed)
+    rng = np.random.default_rng(5000 + seed)
+    q, B, O, ref = w["q"], w["B"], w["O"], w["ref"]
+    n_bins = (ref.size + B - 1) // B
+    n_reads = w["read_len"].size
+    reads = [w["codes"][int(o):int(o) + int(L)] for o, L in zip(w["read_off"], w["read_len"])]
+    sizes = rng.integers(1, 301, n_reads)
+    win_lo = rng.integers(0, n_bins, n_reads)
+    say("random windows", seed, "q", q, "B", B, "bins", n_bins, "pairs", int(sizes.sum()))
+    ww = window_workload(ref, q, B, O, reads, w["read_e"], win_lo, sizes)
+    oc, ob, bad, _ = oracle_run(ww, n_threads=4)
+    idx = g.grim_build_bins(ref, q, B, O)
+    idx.transpose()
+    out = run_windows(g, idx, ww, win_lo)
+    assert_same(out, (oc, ob, bad), f"windows seed {seed}")
+    # seeding
+    k = int(rng.integers(4, 13))
+    cap = int(rng.choice([1, 7, 64, 4096]))
+    say("random seeding", seed, "k", k, "cap", cap)
+    batch = g.Batch(w["codes"], w["read_off"], w["read_len"], w["read_e"], w["e_den"],
+                    np.zeros(n_reads + 1, np.uint64), np.zeros(0, np.uint32))
+    si = g.SeedIndex(ref, k)
+    off, bins = g.grim_seed_candidates(si, batch, B, cap).to_host()
+    w_off, w_bins = oracle.seed_candidates(ref, k, w["codes"], w["read_off"], w["read_len"], B, cap)
+    assert np.array_equal(off, w_off) and np.array_equal(bins, w_bins)
