@@ -253,6 +253,16 @@ __device__ __forceinline__ uint32_t ref_window(const uint32_t *__restrict__ w, u
     return sh ? (w0 << sh) | (w1 >> (32 - sh)) : w0;
 }
 
+// Three-input bitwise function as gfx950's v_bitop3_b32 immediate: the truth
+// table of f read off f(0xF0, 0xCC, 0xAA) (operands a, b, c in that order).
+template <uint32_t IMM>
+__device__ __forceinline__ uint32_t bitop3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, IMM);
+}
+constexpr uint32_t kXorOr = ((0xF0u ^ 0xCCu) | 0xAAu) & 0xFFu;   // (a ^ b) | c
+constexpr uint32_t kOrNor = (0xF0u | ~(0xCCu | 0xAAu)) & 0xFFu;  // a | ~(b | c)
+
 // A workgroup takes 256 survivors at a time and hands them to its threads
 // sorted by the number of 64-row blocks of their read (counting sort in LDS),
 // so that most wavefronts hold reads of one block count and skip the blocks
@@ -308,12 +318,14 @@ __global__ __launch_bounds__(256) void verify_kernel(VerifyArgs a)
             if (r < a.n_reads && b < a.n_bins && L <= 64u * W && off <= nb && L <= nb - off) {
                 const uint32_t E =
                     (uint32_t)(((uint64_t)a.read_e[r] * L + a.e_den - 1) / a.e_den);
-                uint64_t Pv[W], Mv[W];
+                // vertical deltas of each block as 32-bit halves (the VALU is
+                // 32 bits wide): Pv = pvl | pvh << 32, Mv likewise
+                uint32_t pvl[W], pvh[W], mvl[W], mvh[W];
 #pragma unroll
                 for (int w = 0; w < W; ++w) {
                     uint64_t pa = 0, pc = 0, pg = 0, pt = 0;
-                    Pv[w] = ~0ull;
-                    Mv[w] = 0;
+                    pvl[w] = pvh[w] = ~0u;
+                    mvl[w] = mvh[w] = 0u;
                     for (uint32_t k = 0; k < 64; ++k) {
                         const uint32_t p = 64u * w + k;
                         if (p >= L)
@@ -332,6 +344,16 @@ __global__ __launch_bounds__(256) void verify_kernel(VerifyArgs a)
                 }
                 const int wu = (int)((L + 63) >> 6);
                 const uint32_t last_bit = (L - 1) & 63;    // the read's last row in its last block
+                // the row whose horizontal delta leaves each block: 63, or the
+                // read's last row in its last block (which half, which bit)
+                bool out_hi[W];
+                uint32_t out_sh[W];
+#pragma unroll
+                for (int w = 0; w < W; ++w) {
+                    const uint32_t tb = (w == wu - 1) ? last_bit : 63u;
+                    out_hi[w] = tb >= 32;
+                    out_sh[w] = tb & 31;
+                }
                 const uint64_t lo = (uint64_t)b * a.B;
                 uint64_t hi = lo + a.B + a.O;
                 if (hi > a.G)
@@ -352,24 +374,38 @@ __global__ __launch_bounds__(256) void verify_kernel(VerifyArgs a)
                     for (int w = 0; w < W; ++w)
                         eqw[w] = pq[w * 256];
                     // horizontal delta leaving a block's bottom row: +1 (hp = 1),
-                    // -1 (hm = 1) or 0, carried into the next block as 0/1 words;
-                    // the boundary row above block 0 contributes 0
-                    uint64_t hp = 0, hm = 0;
+                    // -1 (hm = 1) or 0, carried into the next block as 0/1 bits;
+                    // the boundary row above block 0 contributes 0.  Per block:
+                    //   Xv = Eq | Mv;  Eq |= hm;  Xh = (((Eq & Pv) + Pv) ^ Pv) | Eq
+                    //   Ph = Mv | ~(Xh | Pv);  Mh = Pv & Xh   (out: their bottom bits)
+                    //   Ph = Ph << 1 | hp;  Mh = Mh << 1 | hm
+                    //   Pv = Mh | ~(Xv | Ph);  Mv = Ph & Xv
+                    uint32_t hp = 0, hm = 0;
 #pragma unroll
                     for (int w = 0; w < W; ++w) {
                         if (w < wu) {
-                            uint64_t eq = eqw[w];
-                            const uint64_t xv = eq | Mv[w];
-                            eq |= hm;
-                            const uint64_t xh = (((eq & Pv[w]) + Pv[w]) ^ Pv[w]) | eq;
-                            uint64_t ph = Mv[w] | ~(xh | Pv[w]);
-                            uint64_t mh = Pv[w] & xh;
-                            const uint32_t tb = (w == wu - 1) ? last_bit : 63u;
-                            const uint64_t hp_out = (ph >> tb) & 1ull, hm_out = (mh >> tb) & 1ull;
-                            ph = (ph << 1) | hp;
-                            mh = (mh << 1) | hm;
-                            Pv[w] = mh | ~(xv | ph);
-                            Mv[w] = ph & xv;
+                            uint32_t el = (uint32_t)eqw[w];
+                            const uint32_t eh = (uint32_t)(eqw[w] >> 32);
+                            const uint32_t xvl = el | mvl[w], xvh = eh | mvh[w];
+                            el |= hm;
+                            const uint64_t sum =
+                                (((uint64_t)(eh & pvh[w]) << 32) | (el & pvl[w])) +
+                                (((uint64_t)pvh[w] << 32) | pvl[w]);
+                            const uint32_t xhl = bitop3<kXorOr>((uint32_t)sum, pvl[w], el);
+                            const uint32_t xhh = bitop3<kXorOr>((uint32_t)(sum >> 32), pvh[w], eh);
+                            uint32_t phl = bitop3<kOrNor>(mvl[w], xhl, pvl[w]);
+                            uint32_t phh = bitop3<kOrNor>(mvh[w], xhh, pvh[w]);
+                            uint32_t mhl = pvl[w] & xhl, mhh = pvh[w] & xhh;
+                            const uint32_t hp_out = ((out_hi[w] ? phh : phl) >> out_sh[w]) & 1u;
+                            const uint32_t hm_out = ((out_hi[w] ? mhh : mhl) >> out_sh[w]) & 1u;
+                            phh = __builtin_amdgcn_alignbit(phh, phl, 31);
+                            phl = (phl << 1) | hp;
+                            mhh = __builtin_amdgcn_alignbit(mhh, mhl, 31);
+                            mhl = (mhl << 1) | hm;
+                            pvl[w] = bitop3<kOrNor>(mhl, xvl, phl);
+                            pvh[w] = bitop3<kOrNor>(mhh, xvh, phh);
+                            mvl[w] = phl & xvl;
+                            mvh[w] = phh & xvh;
                             hp = hp_out;
                             hm = hm_out;
                         }
