@@ -388,11 +388,12 @@ __global__ __launch_bounds__(256) void verify_kernel(VerifyArgs a)
                             const uint32_t eh = (uint32_t)(eqw[w] >> 32);
                             const uint32_t xvl = el | mvl[w], xvh = eh | mvh[w];
                             el |= hm;
-                            const uint64_t sum =
-                                (((uint64_t)(eh & pvh[w]) << 32) | (el & pvl[w])) +
-                                (((uint64_t)pvh[w] << 32) | pvl[w]);
-                            const uint32_t xhl = bitop3<kXorOr>((uint32_t)sum, pvl[w], el);
-                            const uint32_t xhh = bitop3<kXorOr>((uint32_t)(sum >> 32), pvh[w], eh);
+                            // (Eq & Pv) + Pv over the 64 rows: low half, carry, high half
+                            const uint32_t tl = el & pvl[w];
+                            const uint32_t sl = tl + pvl[w];
+                            const uint32_t sh = (eh & pvh[w]) + pvh[w] + (sl < tl ? 1u : 0u);
+                            const uint32_t xhl = bitop3<kXorOr>(sl, pvl[w], el);
+                            const uint32_t xhh = bitop3<kXorOr>(sh, pvh[w], eh);
                             uint32_t phl = bitop3<kOrNor>(mvl[w], xhl, pvl[w]);
                             uint32_t phh = bitop3<kOrNor>(mvh[w], xhh, pvh[w]);
                             uint32_t mhl = pvl[w] & xhl, mhh = pvh[w] & xhh;
