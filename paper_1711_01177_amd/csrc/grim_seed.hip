@@ -308,6 +308,8 @@ hipError_t scan_u64(hipStream_t s, const void *in, bool in_u32, uint64_t n, uint
     return hipGetLastError();
 }
 
+uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+
 uint64_t scan_blocks(uint64_t n) { return std::max<uint64_t>(1, (n + kScanPerBlock - 1) / kScanPerBlock); }
 
 uint32_t grid_for(uint64_t threads, int dev)
@@ -420,6 +422,7 @@ extern "C" int grim_seed_candidates(const grim_seed_index_t *si, const grim_batc
     uint64_t *hits = nullptr, *hit_off = nullptr, *btmp = nullptr, *ucnt = nullptr;
     uint32_t *hb = nullptr, *hs = nullptr;
     void *sort_tmp = nullptr;
+    uint8_t *tmp_reads = nullptr, *tmp_hits = nullptr;  // temporaries, two allocations
     size_t sort_bytes = 0;
     uint64_t total_hits = 0, n_pairs = 0;
     grim_candidates *c = new (std::nothrow) grim_candidates();
@@ -429,11 +432,18 @@ extern "C" int grim_seed_candidates(const grim_seed_index_t *si, const grim_batc
     c->d_off = nullptr;
     c->d_bin = nullptr;
     const uint64_t nbt = scan_blocks(n) + 1;
-    if (hipMalloc(&hits, (n + 1) * 8) != hipSuccess || hipMalloc(&hit_off, (n + 1) * 8) != hipSuccess ||
-        hipMalloc(&btmp, nbt * 8) != hipSuccess || hipMalloc(&ucnt, (n + 1) * 8) != hipSuccess ||
-        hipMalloc(&c->d_off, (n + 1) * 8) != hipSuccess) {
-        rc = GRIM_E_NOMEM;
-        goto done;
+    {
+        // per-read temporaries: hit counts, hit offsets, scan block sums, unique counts
+        const uint64_t r8 = align_up((n + 1) * 8, 256), b8 = align_up(nbt * 8, 256);
+        if (hipMalloc(&tmp_reads, 3 * r8 + b8) != hipSuccess ||
+            hipMalloc(&c->d_off, (n + 1) * 8) != hipSuccess) {
+            rc = GRIM_E_NOMEM;
+            goto done;
+        }
+        hits = reinterpret_cast<uint64_t *>(tmp_reads);
+        hit_off = reinterpret_cast<uint64_t *>(tmp_reads + r8);
+        ucnt = reinterpret_cast<uint64_t *>(tmp_reads + 2 * r8);
+        btmp = reinterpret_cast<uint64_t *>(tmp_reads + 3 * r8);
     }
     if (n) {
         hipLaunchKernelGGL(seed_count_kernel, dim3(grid_for(n, dev)), dim3(256), 0, s,
@@ -448,10 +458,23 @@ extern "C" int grim_seed_candidates(const grim_seed_index_t *si, const grim_batc
         rc = GRIM_E_UNSUPPORTED;
         goto done;
     }
-    if (hipMalloc(&hb, (total_hits + 1) * 4) != hipSuccess ||
-        hipMalloc(&hs, (total_hits + 1) * 4) != hipSuccess) {
-        rc = GRIM_E_NOMEM;
-        goto done;
+    if (n) {
+        // per-hit temporaries: hit bins, sorted hit bins, the sort's own storage
+        SEED_TRY(hipcub::DeviceSegmentedRadixSort::SortKeys(
+            nullptr, sort_bytes, static_cast<const uint32_t *>(nullptr),
+            static_cast<uint32_t *>(nullptr), (int)total_hits, (int)n, hit_off, hit_off + 1, 0, 32,
+            s));
+    }
+    {
+        const uint64_t h4 = align_up((total_hits + 1) * 4, 256);
+        if (hipMalloc(&tmp_hits, 2 * h4 + align_up(sort_bytes ? sort_bytes : 1, 256)) !=
+            hipSuccess) {
+            rc = GRIM_E_NOMEM;
+            goto done;
+        }
+        hb = reinterpret_cast<uint32_t *>(tmp_hits);
+        hs = reinterpret_cast<uint32_t *>(tmp_hits + h4);
+        sort_tmp = tmp_hits + 2 * h4;
     }
     if (n) {
         hipLaunchKernelGGL(seed_emit_kernel, dim3(grid_for(n * 64, dev)), dim3(256), 0, s,
@@ -459,13 +482,6 @@ extern "C" int grim_seed_candidates(const grim_seed_index_t *si, const grim_batc
                            reads->read_len, n, si->k, si->d_off, si->d_pos, si->G, bin_stride,
                            hit_off, hb);
         SEED_TRY(hipGetLastError());
-        SEED_TRY(hipcub::DeviceSegmentedRadixSort::SortKeys(nullptr, sort_bytes, hb, hs,
-                                                            (int)total_hits, (int)n, hit_off,
-                                                            hit_off + 1, 0, 32, s));
-        if (hipMalloc(&sort_tmp, sort_bytes ? sort_bytes : 1) != hipSuccess) {
-            rc = GRIM_E_NOMEM;
-            goto done;
-        }
         SEED_TRY(hipcub::DeviceSegmentedRadixSort::SortKeys(sort_tmp, sort_bytes, hb, hs,
                                                             (int)total_hits, (int)n, hit_off,
                                                             hit_off + 1, 0, 32, s));
@@ -488,13 +504,8 @@ extern "C" int grim_seed_candidates(const grim_seed_index_t *si, const grim_batc
     SEED_TRY(hipStreamSynchronize(s));
     c->n_pairs = n_pairs;
 done:
-    (void)hipFree(hits);
-    (void)hipFree(hit_off);
-    (void)hipFree(btmp);
-    (void)hipFree(ucnt);
-    (void)hipFree(hb);
-    (void)hipFree(hs);
-    (void)hipFree(sort_tmp);
+    (void)hipFree(tmp_reads);
+    (void)hipFree(tmp_hits);
     if (rc != GRIM_OK) {
         (void)hipFree(c->d_off);
         (void)hipFree(c->d_bin);
