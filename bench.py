@@ -145,7 +145,7 @@ def link_probe(torch, n_bytes=256 << 20, reps=5):
 
 def serving_leg(g, idx, w, rng, loads=(0.25, 0.5, 0.75, 0.9), n_requests=10_000, pool=256,
                 max_reads=65536, inplace=True, tick_pairs=8 << 20, n_streams=3,
-                max_inflight=1024, fixed_rates=None):
+                max_inflight=1024, fixed_rates=None, bits_only=False):
     """Served latency.  A pool of `pool` requests of log-uniform size
     (1..max_reads reads) is cut from the workload.  First the server's capacity
     is measured closed-loop (a burst of requests submitted at once); then, for
@@ -158,7 +158,8 @@ def serving_leg(g, idx, w, rng, loads=(0.25, 0.5, 0.75, 0.9), n_requests=10_000,
     hold at most tick_pairs pairs, so larger requests run in parts; n_streams
     ticks (and at most max_inflight requests) are in flight at once.  fixed_rates (pairs per second)
     replaces the loads relative to capacity by absolute arrival rates, so that
-    server configurations can be compared at the same offered traffic."""
+    server configurations can be compared at the same offered traffic.
+    bits_only=True serves the pass bits alone (counts stay on the device)."""
     n_reads = w["read_len"].size
     reqs = []
     for _ in range(pool):
@@ -173,7 +174,7 @@ def serving_leg(g, idx, w, rng, loads=(0.25, 0.5, 0.75, 0.9), n_requests=10_000,
                                 w["cand_bin"][c0:c1], max_len=250, pinned=inplace))
     mean_pairs = float(np.mean([hb.n_pairs for hb in reqs]))
     srv = g.Server(idx, hbm_budget_bytes=4 << 30, max_inflight=max_inflight, n_streams=n_streams,
-                   max_tick_pairs=tick_pairs, max_len=256)
+                   max_tick_pairs=tick_pairs, max_len=256, pass_bits_only=bits_only)
     submit = srv.submit_inplace if inplace else srv.submit
 
     def finish(rc, ticket):
@@ -200,8 +201,10 @@ def serving_leg(g, idx, w, rng, loads=(0.25, 0.5, 0.75, 0.9), n_requests=10_000,
     # pass bits (the tick's bits via the stage, then ORed in) back
     n_pairs_all = sum(hb.n_pairs for hb in reqs)
     up_bytes = sum(hb.words.size * 4 + hb.n_reads * 24 + 8 + hb.n_pairs * 4 for hb in reqs)
-    down_bytes = sum(hb.n_pairs * 4 + ((hb.n_pairs + 31) // 32) * 4 for hb in reqs)
-    out = dict(mode="in place, pinned buffers" if inplace else "copying submission",
+    down_bytes = sum((0 if bits_only else hb.n_pairs * 4) + ((hb.n_pairs + 31) // 32) * 4
+                     for hb in reqs)
+    out = dict(mode=("in place, pinned buffers" if inplace else "copying submission") +
+               (", pass bits only" if bits_only else ""),
                pool_requests=pool, mean_pairs_per_request=mean_pairs,
                max_tick_pairs=tick_pairs, n_streams=n_streams, max_inflight=max_inflight,
                capacity_burst_s=walls,
@@ -718,9 +721,22 @@ def main():
                 log(f"[bench] serving at {pt['offered_load']:.2f} x capacity "
                     f"({pt['offered_rps']:.0f} req/s): p50 {pt['p50_ms']:.2f} ms "
                     f"p99 {pt['p99_ms']:.2f} ms, {pt['pairs_per_s']:.3e} pairs/s")
+            bo = serving_leg(g, idx, w, rng, loads=(0.25, 0.5), n_requests=args.serve_requests,
+                             inplace=True, bits_only=True)
+            # pass bits only: the host-to-device direction alone decides
+            bo_ceiling = link["h2d_gbs"] * 1e9 / bo["link_bytes_per_pair"]["up"]
+            bo["link"] = dict(ceiling_pairs_per_s=bo_ceiling,
+                              capacity_frac_of_ceiling=bo["capacity_pairs_per_s"] / bo_ceiling)
+            serving["pass_bits_only"] = bo
+            for pt in bo["points"]:
+                log(f"[bench] serving pass bits only at {pt['offered_load']:.2f} x capacity "
+                    f"({pt['offered_rps']:.0f} req/s): p50 {pt['p50_ms']:.2f} ms "
+                    f"p99 {pt['p99_ms']:.2f} ms, {pt['pairs_per_s']:.3e} pairs/s")
             log(f"[bench] serving capacity {serving['capacity_pairs_per_s']:.3e} pairs/s in place "
                 f"({100 * serving['link']['capacity_frac_of_ceiling']:.0f} % of the link ceiling), "
-                f"{serving['copying_submission']['capacity_pairs_per_s']:.3e} copying "
+                f"{serving['copying_submission']['capacity_pairs_per_s']:.3e} copying, "
+                f"{bo['capacity_pairs_per_s']:.3e} pass bits only "
+                f"({100 * bo['link']['capacity_frac_of_ceiling']:.0f} % of its ceiling) "
                 f"({time.time() - t0:.1f}s)")
         except Exception as ex:  # report, keep the throughput line
             serving = dict(error=str(ex))

@@ -369,6 +369,16 @@ void grim_graph_destroy(grim_graph_t *g);
  * Parallelization"). */
 typedef struct grim_server grim_server_t;
 
+/* Server option: a request's results are its pass bits alone (the seed
+ * location filter bitmask of Section "Integration with a Full Read Mapper");
+ * its counts stay on the device, so each pair moves 1/8 byte back over the
+ * host link instead of 4 1/8 bytes, and the counts buffers of
+ * grim_serve_submit_inplace, grim_serve_poll and grim_serve_wait may be NULL
+ * (they are left untouched).  A request with an out-of-range bin id still
+ * fails alone with GRIM_E_BIN_RANGE: only a tick whose status word flags one
+ * copies its counts back to find it. */
+#define GRIM_SERVE_PASS_BITS_ONLY 1u
+
 typedef struct grim_serve_cfg {
     uint64_t hbm_budget_bytes;  /* device bytes for request buffers (0 = 1 GiB)     */
     uint32_t max_inflight;      /* requests on the device at once (0 = 1024)        */
@@ -376,6 +386,7 @@ typedef struct grim_serve_cfg {
     uint32_t max_tick_pairs;    /* pairs per launch; larger requests run in parts
                                    of whole reads (0 = 8M)                          */
     uint32_t max_len;           /* longest read accepted (0 = 1024)                 */
+    uint32_t flags;             /* GRIM_SERVE_* options (0: counts and pass bits)   */
 } grim_serve_cfg_t;
 
 typedef struct grim_req_stats {

@@ -45,6 +45,7 @@ GRIM_E_TIMEOUT = -10
 GRIM_E_READ = -11
 GRIM_FLAG_BIN_RANGE = 1
 GRIM_FLAG_READ = 2
+GRIM_SERVE_PASS_BITS_ONLY = 1
 GRIM_FLAG_CAND_OFF = 4
 
 _u8p = ctypes.POINTER(ctypes.c_uint8)
@@ -87,7 +88,7 @@ class grim_tuning_t(ctypes.Structure):
 
 class grim_serve_cfg_t(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", _u64), ("max_inflight", _u32), ("n_streams", _u32),
-                ("max_tick_pairs", _u32), ("max_len", _u32)]
+                ("max_tick_pairs", _u32), ("max_len", _u32), ("flags", _u32)]
 
 
 class grim_req_stats_t(ctypes.Structure):
@@ -689,10 +690,12 @@ class Server:
     """Continuous-batching server over a resident index (owns a grim_server_t)."""
 
     def __init__(self, index, hbm_budget_bytes=0, max_inflight=0, n_streams=0, max_tick_pairs=0,
-                 max_len=0):
+                 max_len=0, pass_bits_only=False):
         self.index = index
+        self.pass_bits_only = bool(pass_bits_only)
         cfg = grim_serve_cfg_t(int(hbm_budget_bytes), int(max_inflight), int(n_streams),
-                               int(max_tick_pairs), int(max_len))
+                               int(max_tick_pairs), int(max_len),
+                               GRIM_SERVE_PASS_BITS_ONLY if pass_bits_only else 0)
         self._h = ctypes.c_void_p()
         _check(_lib.grim_serve_create(index.handle, ctypes.byref(cfg), ctypes.byref(self._h)),
                "grim_serve_create")
@@ -724,15 +727,18 @@ class Server:
             counts, bits = hb.out_counts, hb.out_bits
         else:
             n = pend
-            counts = np.empty(max(1, n), dtype=np.int32)
+            counts = None if self.pass_bits_only else np.empty(max(1, n), dtype=np.int32)
             bits = np.empty(max(1, (n + 31) // 32), dtype=np.uint32)
         st = grim_req_stats_t()
-        rc = fn(self._h, int(ticket), *extra, counts.ctypes.data_as(_vp),
+        rc = fn(self._h, int(ticket), *extra,
+                counts.ctypes.data_as(_vp) if counts is not None else None,
                 bits.ctypes.data_as(_vp), ctypes.byref(st))
         if rc in (GRIM_PENDING, GRIM_E_TIMEOUT):
             return rc, None, None, None
         self._pending.pop(ticket, None)
-        return rc, counts[:n], bits[:(n + 31) // 32], st
+        # with pass bits only the counts are not results (an in-place batch's
+        # count buffer is left as it was)
+        return rc, (None if self.pass_bits_only else counts[:n]), bits[:(n + 31) // 32], st
 
     def poll(self, ticket):
         return self._result(_lib.grim_serve_poll, ticket)

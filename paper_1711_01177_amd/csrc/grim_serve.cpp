@@ -397,16 +397,30 @@ void grim_server::retire(Slot &s)
     const int32_t *counts = reinterpret_cast<const int32_t *>(out + s.lay.counts);
     const uint32_t *bits = reinterpret_cast<const uint32_t *>(out + s.lay.bits);
     const uint32_t status = *reinterpret_cast<const uint32_t *>(out + s.lay.status);
+    const bool bits_only = (cfg.flags & GRIM_SERVE_PASS_BITS_ONLY) != 0;
+    if (bits_only && (status & GRIM_FLAG_BIN_RANGE)) {
+        // the counts stayed on the device: fetch this tick's to find the -1s
+        uint64_t n = 0;
+        for (const Part &pt : s.parts)
+            n = std::max(n, pt.fused_base + (pt.pb - pt.pa));
+        const uint8_t *dout = pool_base + s.dev_off + s.lay.out_base;
+        if (hipMemcpyAsync(s.stage + s.lay.out_base + s.lay.counts, dout + s.lay.counts, n * 4,
+                           hipMemcpyDeviceToHost, s.stream) != hipSuccess ||
+            hipStreamSynchronize(s.stream) != hipSuccess) {
+            for (Part &pt : s.parts)  // cannot tell which: fail them all
+                pt.r->status = GRIM_E_HIP;
+        }
+    }
     const auto now = Clock::now();
     for (Part &pt : s.parts) {
         Request &r = *pt.r;
         const uint64_t np = pt.pb - pt.pa;
         if (!r.cancelled && np) {
-            if (!pt.counts_direct)
+            if (!bits_only && !pt.counts_direct)
                 std::memcpy(r.counts() + pt.pa, counts + pt.fused_base, np * 4);
             or_bits(r.bits(), pt.pa, bits, pt.fused_base, np);
             if (status & GRIM_FLAG_BIN_RANGE) {  // only then look for -1 in this part
-                const int32_t *c = r.counts() + pt.pa;
+                const int32_t *c = bits_only ? counts + pt.fused_base : r.counts() + pt.pa;
                 for (uint64_t k = 0; k < np; ++k)
                     if (c[k] < 0) {
                         r.flags |= GRIM_FLAG_BIN_RANGE;
@@ -670,8 +684,10 @@ bool grim_server::launch_tick(std::unique_lock<std::mutex> &lk)
         if (rc == GRIM_OK)
             rc = grim_filter_batch(idx, &b, dcounts, dbits, d + lay.ws, lay.ws_bytes, nullptr, st);
         // results: large count slices straight into the request's result area,
-        // the rest (small slices, all pass bits, the status word) via the stage
+        // the rest (small slices, all pass bits, the status word) via the stage;
+        // no counts at all when only the pass bits are results
         if (rc == GRIM_OK) {
+            const bool bits_only = (cfg.flags & GRIM_SERVE_PASS_BITS_ONLY) != 0;
             uint64_t run_lo = 0, run_hi = 0;
             bool run = false;
             auto flush = [&] {
@@ -680,7 +696,7 @@ bool grim_server::launch_tick(std::unique_lock<std::mutex> &lk)
                                        hipMemcpyDeviceToHost, st);
                 run = false;
             };
-            for (size_t j = 0; j < take.size() && e == hipSuccess; ++j) {
+            for (size_t j = 0; j < take.size() && e == hipSuccess && !bits_only; ++j) {
                 Part &pt = take[j];
                 const uint64_t lo = lay.counts + pt.fused_base * 4, nb = (pt.pb - pt.pa) * 4;
                 if (nb >= kDirectBytes) {
@@ -779,7 +795,7 @@ extern "C" int grim_serve_create(const grim_index_t *idx, const grim_serve_cfg_t
         c.max_tick_pairs = 8u << 20;
     if (!c.max_len)
         c.max_len = 1024;
-    if (c.max_len > grim::kMaxLen || c.n_streams > 16)
+    if (c.max_len > grim::kMaxLen || c.n_streams > 16 || (c.flags & ~GRIM_SERVE_PASS_BITS_ONLY))
         return GRIM_E_INVALID;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev != idx->device)
@@ -931,7 +947,7 @@ extern "C" int grim_serve_submit_inplace(grim_server_t *s, const grim_batch_t *b
     if (rc)
         return rc;
     const uint64_t n = b->n_reads, P = b->n_pairs;
-    if (P && (!counts || !pass_bits))
+    if (P && (!pass_bits || (!counts && !(s->cfg.flags & GRIM_SERVE_PASS_BITS_ONLY))))
         return GRIM_E_INVALID;
     auto r = std::make_shared<Request>();
     r->in_place = true;
@@ -963,8 +979,9 @@ static int finish(grim_server_t *s, std::unique_lock<std::mutex> &lk,
     Request &r = *rp;
     s->all.erase(it);
     lk.unlock();
+    const bool bits_only = (s->cfg.flags & GRIM_SERVE_PASS_BITS_ONLY) != 0;
     if ((r.status == GRIM_OK || r.status == GRIM_E_BIN_RANGE) && r.counts()) {
-        if (counts && counts != r.counts())
+        if (counts && counts != r.counts() && !bits_only)
             par_memcpy(counts, r.counts(), r.n_pairs * 4);
         if (pass_bits && pass_bits != r.bits())
             std::memcpy(pass_bits, r.bits(), ((r.n_pairs + 31) / 32) * 4);

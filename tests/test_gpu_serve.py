@@ -258,6 +258,43 @@ def test_pageable_inplace_submission(setup):
         srv.destroy()
 
 
+def test_pass_bits_only(setup):
+    """Servers that return pass bits alone: every request's bits equal its solo
+    run, copied and in place, whole and in parts; counts are not returned and
+    in-place count buffers are left as they were; a request with an
+    out-of-range bin id still fails alone (its tick fetches its counts)."""
+    g, w, idx = setup
+    reqs = make_requests(g, w, 16, 23, max_reads=1200)
+    bad_sub, _ = reqs[3]
+    bad_sub["cand_bin"][len(bad_sub["cand_bin"]) // 2] = idx.n_bins + 7
+    reqs[3] = (bad_sub, g.HostBatch(bad_sub["codes"], bad_sub["read_off"], bad_sub["read_len"],
+                                    bad_sub["read_e"], bad_sub["e_den"], bad_sub["cand_off"],
+                                    bad_sub["cand_bin"], max_len=256))
+    solo = [alone(g, idx, sub) for sub, _ in reqs]
+    assert solo[3][0] == g.GRIM_E_BIN_RANGE
+    for tick_pairs in (0, 3000):
+        pinned = [g.HostBatch(sub["codes"], sub["read_off"], sub["read_len"], sub["read_e"],
+                              sub["e_den"], sub["cand_off"], sub["cand_bin"], max_len=256,
+                              pinned=True) for sub, _ in reqs]
+        for hb in pinned:
+            hb.out_counts[:] = -5
+        srv = g.Server(idx, hbm_budget_bytes=64 << 20, max_inflight=64, n_streams=3,
+                       max_tick_pairs=tick_pairs, max_len=256, pass_bits_only=True)
+        ts = [srv.submit_inplace(pinned[i]) if i % 2 else srv.submit(hb)
+              for i, (_, hb) in enumerate(reqs)]
+        for i, t in enumerate(ts):
+            rc, c, b, st = srv.wait(t)
+            assert c is None
+            assert rc == solo[i][0], (tick_pairs, i, rc)
+            assert np.array_equal(b, solo[i][2]), f"{tick_pairs}: request {i} pass bits"
+            if i % 2:
+                assert np.all(pinned[i].out_counts == -5)
+        s = srv.stats()
+        say("bits only", tick_pairs, s)
+        assert s["completed"] == len(reqs)
+        srv.destroy()
+
+
 def test_requests_split_into_parts(setup):
     """Requests with more pairs than max_tick_pairs run in parts of whole reads
     (at 100 pairs down to single reads with more candidates than the limit):
