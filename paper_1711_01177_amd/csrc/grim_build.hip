@@ -1,8 +1,8 @@
 // Chunked bin build for gfx950.
 //
 // Bin b holds every token whose Q bases lie inside [b*B, min(G, (b+1)*B + O))
-// (Section "GRIM-Filter Operation": one existence bitvector per overlapping
-// bin), i.e. the token starts p with b*B <= p <= (b+1)*B + O - Q and
+// (Section "Genome Metadata Representation": one existence bitvector per
+// overlapping bin), i.e. the token starts p with b*B <= p <= (b+1)*B + O - Q and
 // p + Q <= G.  Those are S = B + O - Q + 1 consecutive starts: m = S / B whole
 // blocks of B starts, then the first R = S % B starts of the next block.  With
 // P_j the token set of the first R starts of block j (starts [j*B, (j+1)*B))
