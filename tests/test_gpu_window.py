@@ -35,7 +35,7 @@ def window_workload(ref, q, B, O, reads, e_nums, win_lo, sizes):
     return custom_workload(ref, q, B, O, reads, cands, e_nums)
 
 
-@pytest.mark.parametrize("q,B,O", [(4, 100, 60), (5, 200, 105), (6, 400, 263)])
+@pytest.mark.parametrize("q,B,O", [(4, 100, 60), (5, 200, 105), (6, 400, 263), (7, 300, 60)])
 def test_windows_match_oracle(q, B, O):
     g = lib()
     ref = gs.reference(41 + q, 1_500_000, 0.3, 30, 300, 0.85, 0.98)
