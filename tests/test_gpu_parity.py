@@ -45,13 +45,17 @@ def test_index_parity_params(q, B, O):
 # Bin geometries at the edges of the chunked build: strides below one packed
 # word, spans that end exactly on a block (R = 0, with B >= 16 and below),
 # spans shorter than a token (all-zero vectors), a reference shorter than a
-# token, many whole blocks per bin, and two geometries whose whole blocks exceed the chunk's LDS (q=7 with
-# m = 19, q=4 with m = 598), which take the one-wavefront-per-bin kernel.
+# token, many whole blocks per bin, two geometries whose whole blocks exceed
+# the chunk's LDS (q=7 with m = 19, q=4 with m = 598), which take the
+# one-wavefront-per-bin kernel, a 100 kb stride (three bins), and a stride
+# beyond 2^31 (one bin; offsets inside a chunk would leave 32 bits, so the
+# per-bin kernel again).
 @pytest.mark.parametrize("q,B,O,G", [(5, 10, 3, 3001), (4, 7, 100, 5003), (4, 3, 1, 1001),
                                      (5, 16, 0, 4099), (6, 1, 0, 301), (4, 200, 275, 3),
                                      (5, 1, 40, 777), (7, 5, 60, 2001), (5, 100, 4, 70_001),
                                      (7, 3, 60, 1999), (4, 1, 600, 2500), (5, 20, 4, 5000),
-                                     (5, 20, 24, 5000), (6, 64, 5, 9000), (5, 16, 15, 4000)])
+                                     (5, 20, 24, 5000), (6, 64, 5, 9000), (5, 16, 15, 4000),
+                                     (5, 100_000, 50, 250_003), (4, 3_000_000_000, 0, 5000)])
 def test_index_parity_edges(q, B, O, G):
     say("index parity edge", q, B, O, G)
     ref = np.random.default_rng(q * 1000 + B + G).integers(0, 4, G).astype(np.uint8)
