@@ -236,21 +236,26 @@ uint64_t compact_blocks(uint64_t n_pairs)
 // reference base each block updates its vertical delta vectors (Pv, Mv) and
 // passes the horizontal delta of its last row to the next block.  One thread
 // per survivor; the read's match masks live in registers.
-__device__ __forceinline__ uint32_t base_at(const uint32_t *__restrict__ w, uint64_t nw, uint64_t p)
+// 16 read bases starting at base position pos (any alignment; may start
+// before the array, whose words count as 0 there and past its end), first
+// base in the top bits.
+__device__ __forceinline__ uint32_t read_window(const uint32_t *__restrict__ w, uint64_t nw,
+                                                int64_t pos)
 {
-    const uint64_t wi = p >> 4;
-    const uint32_t x = wi < nw ? w[wi] : 0u;
-    return (x >> (30 - 2 * (uint32_t)(p & 15))) & 3u;
+    const int64_t wi = pos >> 4;   // floor, also for negative positions
+    const uint32_t sh = (uint32_t)(pos & 15) << 1;
+    const uint32_t w0 = wi >= 0 && (uint64_t)wi < nw ? w[wi] : 0u;
+    const uint32_t w1 = wi + 1 >= 0 && (uint64_t)(wi + 1) < nw ? w[wi + 1] : 0u;
+    return (uint32_t)((((uint64_t)w0 << 32) | w1) >> (32 - sh));
 }
 
-// 16 reference bases starting at p (any alignment), first base in the top bits.
-__device__ __forceinline__ uint32_t ref_window(const uint32_t *__restrict__ w, uint64_t nw, uint64_t p)
+// Bits 0, 2, ..., 30 of x gathered into bits 0..15.
+__device__ __forceinline__ uint32_t even_bits(uint32_t x)
 {
-    const uint64_t wi = p >> 4;
-    const uint32_t sh = (uint32_t)(p & 15) << 1;
-    const uint32_t w0 = wi < nw ? w[wi] : 0u;
-    const uint32_t w1 = wi + 1 < nw ? w[wi + 1] : 0u;
-    return sh ? (w0 << sh) | (w1 >> (32 - sh)) : w0;
+    x = (x | (x >> 1)) & 0x33333333u;
+    x = (x | (x >> 2)) & 0x0F0F0F0Fu;
+    x = (x | (x >> 4)) & 0x00FF00FFu;
+    return (x | (x >> 8)) & 0x0000FFFFu;
 }
 
 // Three-input bitwise function as gfx950's v_bitop3_b32 immediate: the truth
@@ -318,55 +323,76 @@ __global__ __launch_bounds__(256) void verify_kernel(VerifyArgs a)
             if (r < a.n_reads && b < a.n_bins && L <= 64u * W && off <= nb && L <= nb - off) {
                 const uint32_t E =
                     (uint32_t)(((uint64_t)a.read_e[r] * L + a.e_den - 1) / a.e_den);
+                // The read fills its blocks from the bottom: the first block
+                // starts with pad = 64 wu - L rows that match every base and
+                // whose initial vertical delta is 0, so they repeat the free
+                // boundary row (distance 0 at every column) and the read's
+                // last row is always bit 63 of its last block.
+                const int wu = (int)((L + 63) >> 6);
+                const uint32_t pad = 64u * (uint32_t)wu - L;
                 // vertical deltas of each block as 32-bit halves (the VALU is
                 // 32 bits wide): Pv = pvl | pvh << 32, Mv likewise
                 uint32_t pvl[W], pvh[W], mvl[W], mvh[W];
 #pragma unroll
                 for (int w = 0; w < W; ++w) {
-                    uint64_t pa = 0, pc = 0, pg = 0, pt = 0;
-                    pvl[w] = pvh[w] = ~0u;
-                    mvl[w] = mvh[w] = 0u;
-                    for (uint32_t k = 0; k < 64; ++k) {
-                        const uint32_t p = 64u * w + k;
-                        if (p >= L)
-                            break;
-                        const uint32_t cb = base_at(a.rw, a.nw, off + p);
-                        const uint64_t bit = 1ull << k;
-                        pa |= cb == 0 ? bit : 0ull;
-                        pc |= cb == 1 ? bit : 0ull;
-                        pg |= cb == 2 ? bit : 0ull;
-                        pt |= cb == 3 ? bit : 0ull;
-                    }
-                    peq[(0 * W + w) * 256 + t] = pa;
-                    peq[(1 * W + w) * 256 + t] = pc;
-                    peq[(2 * W + w) * 256 + t] = pg;
-                    peq[(3 * W + w) * 256 + t] = pt;
-                }
-                const int wu = (int)((L + 63) >> 6);
-                const uint32_t last_bit = (L - 1) & 63;    // the read's last row in its last block
-                // the row whose horizontal delta leaves each block: 63, or the
-                // read's last row in its last block (which half, which bit)
-                bool out_hi[W];
-                uint32_t out_sh[W];
+                    // 16 rows at a time: rows 64 w + 16 g + k (k = 0..15) hold
+                    // read bases i0 + k, i0 = 64 w + 16 g - pad; rows with
+                    // i0 + k < 0 are padding
+                    uint32_t ma[2] = {0u, 0u}, mc[2] = {0u, 0u}, mg[2] = {0u, 0u},
+                             mt[2] = {0u, 0u}, pv[2] = {~0u, ~0u};
+                    if (w < wu) {
 #pragma unroll
-                for (int w = 0; w < W; ++w) {
-                    const uint32_t tb = (w == wu - 1) ? last_bit : 63u;
-                    out_hi[w] = tb >= 32;
-                    out_sh[w] = tb & 31;
+                        for (int g = 0; g < 4; ++g) {
+                            const int i0 = 64 * w + 16 * g - (int)pad;
+                            const uint32_t pm = i0 <= -16 ? 0xFFFFu : i0 >= 0 ? 0u
+                                              : (1u << -i0) - 1u;
+                            // base k in bits 2k (high bit of its code) and 2k + 1 (low bit)
+                            const uint32_t rv = __builtin_bitreverse32(
+                                read_window(a.rw, a.nw, (int64_t)off + i0));
+                            const uint32_t h = rv & 0x55555555u, l = (rv >> 1) & 0x55555555u;
+                            const uint32_t sh = 16 * (g & 1);
+                            const int half = g >> 1;
+                            ma[half] |= (even_bits(~(h | l) & 0x55555555u) | pm) << sh;
+                            mc[half] |= (even_bits(l & ~h) | pm) << sh;
+                            mg[half] |= (even_bits(h & ~l) | pm) << sh;
+                            mt[half] |= (even_bits(h & l) | pm) << sh;
+                            pv[half] &= ~(pm << sh);
+                        }
+                    }
+                    peq[(0 * W + w) * 256 + t] = (uint64_t)ma[1] << 32 | ma[0];
+                    peq[(1 * W + w) * 256 + t] = (uint64_t)mc[1] << 32 | mc[0];
+                    peq[(2 * W + w) * 256 + t] = (uint64_t)mg[1] << 32 | mg[0];
+                    peq[(3 * W + w) * 256 + t] = (uint64_t)mt[1] << 32 | mt[0];
+                    pvl[w] = pv[0];
+                    pvh[w] = pv[1];
+                    mvl[w] = mvh[w] = 0u;
                 }
                 const uint64_t lo = (uint64_t)b * a.B;
                 uint64_t hi = lo + a.B + a.O;
                 if (hi > a.G)
                     hi = a.G;
-                const uint64_t span = hi > lo ? hi - lo : 0;
+                // an empty read matches anywhere with no edits: no columns
+                const uint64_t span = hi > lo && L > 0 ? hi - lo : 0;
                 int32_t score = (int32_t)L, best = (int32_t)L;
+                // 16 reference bases are fetched every 16 columns; their bit
+                // offset inside the first packed word is the span start's,
+                // the same at every fetch.  The first word is in bounds since
+                // lo + j < hi <= G.
+                const uint32_t *rp = a.ref + (lo >> 4);
+                const uint64_t rp_words = a.ref_words - (lo >> 4);
+                const uint32_t wsh = ((uint32_t)lo & 15u) << 1;
+                const uint64_t *peq_t = peq + t;
                 uint32_t win = 0;
                 for (uint64_t j = 0; j < span; ++j) {
-                    if ((j & 15) == 0)
-                        win = ref_window(a.ref, a.ref_words, lo + j);
-                    const uint32_t cb = win >> 30;
-                    win <<= 2;
-                    const uint64_t *pq = peq + cb * W * 256 + t;
+                    const uint32_t col = (uint32_t)j & 15;
+                    if (col == 0) {
+                        const uint64_t k = j >> 4;
+                        const uint64_t w01 = (uint64_t)rp[k] << 32 |
+                                             (k + 1 < rp_words ? rp[k + 1] : 0u);
+                        win = (uint32_t)(w01 >> (32 - wsh));
+                    }
+                    const uint32_t cb = __builtin_amdgcn_ubfe(win, 30 - 2 * col, 2);
+                    const uint64_t *pq = peq_t + cb * (W * 256);
                     // every block's mask for this base, read up front (entries of
                     // blocks past the read's last are read but not used)
                     uint64_t eqw[W];
@@ -377,13 +403,14 @@ __global__ __launch_bounds__(256) void verify_kernel(VerifyArgs a)
                     // -1 (hm = 1) or 0, carried into the next block as 0/1 bits;
                     // the boundary row above block 0 contributes 0.  Per block:
                     //   Xv = Eq | Mv;  Eq |= hm;  Xh = (((Eq & Pv) + Pv) ^ Pv) | Eq
-                    //   Ph = Mv | ~(Xh | Pv);  Mh = Pv & Xh   (out: their bottom bits)
+                    //   Ph = Mv | ~(Xh | Pv);  Mh = Pv & Xh   (out: their bit 63)
                     //   Ph = Ph << 1 | hp;  Mh = Mh << 1 | hm
                     //   Pv = Mh | ~(Xv | Ph);  Mv = Ph & Xv
+                    // Block 0 runs for every lane here (L > 0 whenever a column runs).
                     uint32_t hp = 0, hm = 0;
 #pragma unroll
                     for (int w = 0; w < W; ++w) {
-                        if (w < wu) {
+                        if (w == 0 || w < wu) {
                             uint32_t el = (uint32_t)eqw[w];
                             const uint32_t eh = (uint32_t)(eqw[w] >> 32);
                             const uint32_t xvl = el | mvl[w], xvh = eh | mvh[w];
@@ -397,8 +424,8 @@ __global__ __launch_bounds__(256) void verify_kernel(VerifyArgs a)
                             uint32_t phl = bitop3<kOrNor>(mvl[w], xhl, pvl[w]);
                             uint32_t phh = bitop3<kOrNor>(mvh[w], xhh, pvh[w]);
                             uint32_t mhl = pvl[w] & xhl, mhh = pvh[w] & xhh;
-                            const uint32_t hp_out = ((out_hi[w] ? phh : phl) >> out_sh[w]) & 1u;
-                            const uint32_t hm_out = ((out_hi[w] ? mhh : mhl) >> out_sh[w]) & 1u;
+                            const uint32_t hp_out = phh >> 31;
+                            const uint32_t hm_out = mhh >> 31;
                             phh = __builtin_amdgcn_alignbit(phh, phl, 31);
                             phl = (phl << 1) | hp;
                             mhh = __builtin_amdgcn_alignbit(mhh, mhl, 31);
