@@ -231,11 +231,19 @@ uint64_t compact_blocks(uint64_t n_pairs)
 // Smallest edit distance between a surviving read and any substring of its
 // bin's span (free start and end in the reference), i.e. whether the
 // location really holds the read within E edits.  Computed with Myers'
-// bit-parallel approximate-matching recurrence (G. Myers, J. ACM 46(3), 1999),
-// in its block form: the read is split into W 64-row blocks; for every
-// reference base each block updates its vertical delta vectors (Pv, Mv) and
-// passes the horizontal delta of its last row to the next block.  One thread
-// per survivor; the read's match masks live in registers.
+// bit-parallel approximate-matching recurrence (G. Myers, J. ACM 46(3), 1999)
+// on one long bit vector per column: row i of the dynamic-programming
+// column is bit i of a vector of 32-bit words, and the addition and the
+// one-row shifts carry from word to word.  One thread per survivor; the
+// vertical deltas live in registers, the read's match masks in LDS.
+//
+// The read fills the vector from the bottom: the rows above it match every
+// base and start with vertical delta 0, so they repeat the free boundary row
+// (distance 0 at every column, nothing carried out of them), and the read's
+// last row is always bit 31 of the last word.  A wavefront therefore runs the
+// words from the first one any of its lanes needs to the last, with no
+// per-lane branching inside a column.
+
 // 16 read bases starting at base position pos (any alignment; may start
 // before the array, whose words count as 0 there and past its end), first
 // base in the top bits.
@@ -268,18 +276,107 @@ __device__ __forceinline__ uint32_t bitop3(uint32_t a, uint32_t b, uint32_t c)
 constexpr uint32_t kXorOr = ((0xF0u ^ 0xCCu) | 0xAAu) & 0xFFu;   // (a ^ b) | c
 constexpr uint32_t kOrNor = (0xF0u | ~(0xCCu | 0xAAu)) & 0xFFu;  // a | ~(b | c)
 
+// The column scan over words S..NW-1 of every lane (S is the same for the
+// whole wavefront).  peq_t points at this thread's match masks (64-bit pairs
+// of words, base-major, 256 threads apart); rp/rp_words/wsh locate the span
+// in the packed reference.  Returns the smallest distance at the read's last
+// row over the span's columns (L when the span is empty).  Per column and
+// word, with Pv/Mv the vertical deltas and c the carry of the addition:
+//   Xv = Eq | Mv;  Xh = (((Eq & Pv) + Pv + c) ^ Pv) | Eq
+//   Ph = Mv | ~(Xh | Pv);  Mh = Pv & Xh
+//   Ph, Mh shifted up one row (bit 31 of the word below comes in; 0 at S)
+//   Pv = Mh | ~(Xv | Ph);  Mv = Ph & Xv
+// and the distance at the last row moves by bit 31 of Ph minus that of Mh.
+template <int NW, int S>
+__device__ __forceinline__ int32_t column_scan(const uint64_t *peq_t, uint32_t (&pv)[NW],
+                                               uint32_t (&mv)[NW], const uint32_t *rp,
+                                               uint64_t rp_words, uint32_t wsh, uint64_t span,
+                                               int32_t L)
+{
+    int32_t score = L, best = L;
+    if (span == 0)
+        return best;
+    // Loads run ahead of their use: the two reference words of the next
+    // 16-column fetch one fetch ahead, and each pair of mask words of the
+    // next column as soon as the current column is done with that pair.
+    // Word k of a fetch that is used is in bounds (the columns lie below G);
+    // indexes past the end are clamped (those bases are never used), so the
+    // loads are unconditional and nothing waits on them before their use.
+    const uint64_t last = rp_words - 1;
+    uint32_t win = (uint32_t)(((uint64_t)rp[0] << 32 | rp[1 < last ? 1 : last]) >> (32 - wsh));
+    uint64_t nxt = (uint64_t)rp[1 < last ? 1 : last] << 32 | rp[2 < last ? 2 : last];
+    uint64_t e2[NW / 2];
+    {
+        const uint64_t *pq = peq_t + __builtin_amdgcn_ubfe(win, 30, 2) * (NW / 2 * 256);
+#pragma unroll
+        for (int q = S / 2; q < NW / 2; ++q)
+            e2[q] = pq[q * 256];
+    }
+    for (uint64_t j = 0; j < span; ++j) {
+        // the next column's base (the 16-base window moves on after column 15)
+        const uint32_t col = (uint32_t)j & 15;
+        if (col == 15) {
+            win = (uint32_t)(nxt >> (32 - wsh));
+            const uint64_t k = (j >> 4) + 2;
+            nxt = (uint64_t)rp[k < last ? k : last] << 32 | rp[k + 1 < last ? k + 1 : last];
+        }
+        const uint32_t cbn = __builtin_amdgcn_ubfe(win, 30 - 2 * ((col + 1) & 15), 2);
+        const uint64_t *pqn = peq_t + cbn * (NW / 2 * 256);
+        uint32_t c = 0, php = 0, mhp = 0;
+#pragma unroll
+        for (int k = S; k < NW; ++k) {
+            const uint32_t eq = (k & 1) ? (uint32_t)(e2[k / 2] >> 32) : (uint32_t)e2[k / 2];
+            const uint32_t xv = eq | mv[k];
+            const uint32_t sm = __builtin_addc(eq & pv[k], pv[k], c, &c);
+            const uint32_t xh = bitop3<kXorOr>(sm, pv[k], eq);
+            const uint32_t ph = bitop3<kOrNor>(mv[k], xh, pv[k]);
+            const uint32_t mh = pv[k] & xh;
+            const uint32_t phs = k == S ? ph << 1 : __builtin_amdgcn_alignbit(ph, php, 31);
+            const uint32_t mhs = k == S ? mh << 1 : __builtin_amdgcn_alignbit(mh, mhp, 31);
+            php = ph;
+            mhp = mh;
+            pv[k] = bitop3<kOrNor>(mhs, xv, phs);
+            mv[k] = phs & xv;
+            if (k & 1) {   // pair k / 2 is done with: load the next column's
+                e2[k / 2] = pqn[(k / 2) * 256];
+                __builtin_amdgcn_sched_barrier(0);   // keep the load here
+            }
+        }
+        // +1 when bit 31 of Ph is set, -1 when that of Mh is
+        score += (int32_t)(php >> 31) + ((int32_t)mhp >> 31);
+        best = min(best, score);
+    }
+    return best;
+}
+
+// Picks the scan for the wavefront's first word s (uniform across it).
+template <int NW, int S>
+__device__ __forceinline__ int32_t column_scan_from(int s, const uint64_t *peq_t,
+                                                    uint32_t (&pv)[NW], uint32_t (&mv)[NW],
+                                                    const uint32_t *rp, uint64_t rp_words,
+                                                    uint32_t wsh, uint64_t span, int32_t L)
+{
+    if constexpr (S + 1 < NW) {
+        if (s != S)
+            return column_scan_from<NW, S + 1>(s, peq_t, pv, mv, rp, rp_words, wsh, span, L);
+    }
+    return column_scan<NW, S>(peq_t, pv, mv, rp, rp_words, wsh, span, L);
+}
+
 // A workgroup takes 256 survivors at a time and hands them to its threads
-// sorted by the number of 64-row blocks of their read (counting sort in LDS),
-// so that most wavefronts hold reads of one block count and skip the blocks
-// none of their lanes has; pass bits of the 256 are gathered in LDS and
-// stored as 8 whole words.
+// sorted by the number of 32-row words of their read (counting sort in LDS),
+// so that most wavefronts hold reads of one length class; pass bits of the
+// 256 are gathered in LDS and stored as 8 whole words.  W is the number of
+// 64-row blocks (NW = 2 W words) the batch's longest read needs.
 template <int W>
 __global__ __launch_bounds__(256) void verify_kernel(VerifyArgs a)
 {
+    constexpr int NW = 2 * W;
     __shared__ uint32_t order[256];
-    __shared__ uint32_t cls[W + 1];
+    __shared__ uint32_t cls[NW + 1];
     __shared__ uint32_t okw[8];
-    // match masks of every thread's read: peq[(base * W + block) * 256 + thread]
+    // match masks of every thread's read: peq[(base * W + block) * 256 + thread],
+    // block = rows 64 block .. 64 block + 63 of the bottom-aligned vector
     // (lane-interleaved, so that a wavefront's reads of one column are
     // conflict-free whatever bases its lanes see)
     __shared__ uint64_t peq[4 * W * 256];
@@ -287,7 +384,7 @@ __global__ __launch_bounds__(256) void verify_kernel(VerifyArgs a)
     const uint64_t stride = (uint64_t)gridDim.x * 256;
     const uint64_t n_words = (a.n_surv + 31) / 32;
     for (uint64_t base = (uint64_t)blockIdx.x * 256; base < a.n_surv; base += stride) {
-        // block count of survivor base + t (0 when there is nothing to align)
+        // word count of survivor base + t (0 when there is nothing to align)
         int key = 0;
         {
             const uint64_t i = base + t;
@@ -295,11 +392,11 @@ __global__ __launch_bounds__(256) void verify_kernel(VerifyArgs a)
                 const uint32_t r = a.surv_read[i];
                 if (r < a.n_reads) {
                     const uint32_t L = a.read_len[r];
-                    key = L <= 64u * W ? (int)((L + 63) >> 6) : 0;
+                    key = L <= 32u * NW ? (int)((L + 31) >> 5) : 0;
                 }
             }
         }
-        if (t <= W)
+        if (t <= NW)
             cls[t] = 0;
         if (t < 8)
             okw[t] = 0;
@@ -320,52 +417,49 @@ __global__ __launch_bounds__(256) void verify_kernel(VerifyArgs a)
             const uint64_t nb = a.nw * 16;
             const uint32_t L = r < a.n_reads ? a.read_len[r] : 0u;
             const uint64_t off = r < a.n_reads ? a.read_off[r] : 0u;
-            if (r < a.n_reads && b < a.n_bins && L <= 64u * W && off <= nb && L <= nb - off) {
+            if (r < a.n_reads && b < a.n_bins && L <= 32u * NW && off <= nb && L <= nb - off) {
                 const uint32_t E =
                     (uint32_t)(((uint64_t)a.read_e[r] * L + a.e_den - 1) / a.e_den);
-                // The read fills its blocks from the bottom: the first block
-                // starts with pad = 64 wu - L rows that match every base and
-                // whose initial vertical delta is 0, so they repeat the free
-                // boundary row (distance 0 at every column) and the read's
-                // last row is always bit 63 of its last block.
-                const int wu = (int)((L + 63) >> 6);
-                const uint32_t pad = 64u * (uint32_t)wu - L;
-                // vertical deltas of each block as 32-bit halves (the VALU is
-                // 32 bits wide): Pv = pvl | pvh << 32, Mv likewise
-                uint32_t pvl[W], pvh[W], mvl[W], mvh[W];
+                const int pad = 32 * NW - (int)L;   // rows above the read
+                uint32_t pv[NW], mv[NW];
 #pragma unroll
                 for (int w = 0; w < W; ++w) {
                     // 16 rows at a time: rows 64 w + 16 g + k (k = 0..15) hold
                     // read bases i0 + k, i0 = 64 w + 16 g - pad; rows with
-                    // i0 + k < 0 are padding
+                    // i0 + k < 0 match every base
                     uint32_t ma[2] = {0u, 0u}, mc[2] = {0u, 0u}, mg[2] = {0u, 0u},
-                             mt[2] = {0u, 0u}, pv[2] = {~0u, ~0u};
-                    if (w < wu) {
+                             mt[2] = {0u, 0u}, pw[2] = {~0u, ~0u};
 #pragma unroll
-                        for (int g = 0; g < 4; ++g) {
-                            const int i0 = 64 * w + 16 * g - (int)pad;
-                            const uint32_t pm = i0 <= -16 ? 0xFFFFu : i0 >= 0 ? 0u
-                                              : (1u << -i0) - 1u;
+                    for (int g = 0; g < 4; ++g) {
+                        const int i0 = 64 * w + 16 * g - pad;
+                        const uint32_t sh = 16 * (g & 1);
+                        const int half = g >> 1;
+                        uint32_t xa = 0xFFFFu, xc = 0xFFFFu, xg = 0xFFFFu, xt = 0xFFFFu,
+                                 pm = 0xFFFFu;
+                        if (i0 > -16) {
+                            pm = i0 >= 0 ? 0u : (1u << -i0) - 1u;
                             // base k in bits 2k (high bit of its code) and 2k + 1 (low bit)
                             const uint32_t rv = __builtin_bitreverse32(
                                 read_window(a.rw, a.nw, (int64_t)off + i0));
                             const uint32_t h = rv & 0x55555555u, l = (rv >> 1) & 0x55555555u;
-                            const uint32_t sh = 16 * (g & 1);
-                            const int half = g >> 1;
-                            ma[half] |= (even_bits(~(h | l) & 0x55555555u) | pm) << sh;
-                            mc[half] |= (even_bits(l & ~h) | pm) << sh;
-                            mg[half] |= (even_bits(h & ~l) | pm) << sh;
-                            mt[half] |= (even_bits(h & l) | pm) << sh;
-                            pv[half] &= ~(pm << sh);
+                            xa = even_bits(~(h | l) & 0x55555555u) | pm;
+                            xc = even_bits(l & ~h) | pm;
+                            xg = even_bits(h & ~l) | pm;
+                            xt = even_bits(h & l) | pm;
                         }
+                        ma[half] |= xa << sh;
+                        mc[half] |= xc << sh;
+                        mg[half] |= xg << sh;
+                        mt[half] |= xt << sh;
+                        pw[half] &= ~(pm << sh);
                     }
                     peq[(0 * W + w) * 256 + t] = (uint64_t)ma[1] << 32 | ma[0];
                     peq[(1 * W + w) * 256 + t] = (uint64_t)mc[1] << 32 | mc[0];
                     peq[(2 * W + w) * 256 + t] = (uint64_t)mg[1] << 32 | mg[0];
                     peq[(3 * W + w) * 256 + t] = (uint64_t)mt[1] << 32 | mt[0];
-                    pvl[w] = pv[0];
-                    pvh[w] = pv[1];
-                    mvl[w] = mvh[w] = 0u;
+                    pv[2 * w] = pw[0];
+                    pv[2 * w + 1] = pw[1];
+                    mv[2 * w] = mv[2 * w + 1] = 0u;
                 }
                 const uint64_t lo = (uint64_t)b * a.B;
                 uint64_t hi = lo + a.B + a.O;
@@ -373,7 +467,13 @@ __global__ __launch_bounds__(256) void verify_kernel(VerifyArgs a)
                     hi = a.G;
                 // an empty read matches anywhere with no edits: no columns
                 const uint64_t span = hi > lo && L > 0 ? hi - lo : 0;
-                int32_t score = (int32_t)L, best = (int32_t)L;
+                // the wavefront's first word: the most words any of its
+                // scanning lanes needs, counted from the bottom
+                const uint32_t n = (L + 31) >> 5;
+                int nmax = 0;
+#pragma unroll
+                for (int v = 1; v <= NW; ++v)
+                    nmax += __builtin_amdgcn_ballot_w64(n >= (uint32_t)v) != 0;
                 // 16 reference bases are fetched every 16 columns; their bit
                 // offset inside the first packed word is the span start's,
                 // the same at every fetch.  The first word is in bounds since
@@ -381,66 +481,8 @@ __global__ __launch_bounds__(256) void verify_kernel(VerifyArgs a)
                 const uint32_t *rp = a.ref + (lo >> 4);
                 const uint64_t rp_words = a.ref_words - (lo >> 4);
                 const uint32_t wsh = ((uint32_t)lo & 15u) << 1;
-                const uint64_t *peq_t = peq + t;
-                uint32_t win = 0;
-                for (uint64_t j = 0; j < span; ++j) {
-                    const uint32_t col = (uint32_t)j & 15;
-                    if (col == 0) {
-                        const uint64_t k = j >> 4;
-                        const uint64_t w01 = (uint64_t)rp[k] << 32 |
-                                             (k + 1 < rp_words ? rp[k + 1] : 0u);
-                        win = (uint32_t)(w01 >> (32 - wsh));
-                    }
-                    const uint32_t cb = __builtin_amdgcn_ubfe(win, 30 - 2 * col, 2);
-                    const uint64_t *pq = peq_t + cb * (W * 256);
-                    // every block's mask for this base, read up front (entries of
-                    // blocks past the read's last are read but not used)
-                    uint64_t eqw[W];
-#pragma unroll
-                    for (int w = 0; w < W; ++w)
-                        eqw[w] = pq[w * 256];
-                    // horizontal delta leaving a block's bottom row: +1 (hp = 1),
-                    // -1 (hm = 1) or 0, carried into the next block as 0/1 bits;
-                    // the boundary row above block 0 contributes 0.  Per block:
-                    //   Xv = Eq | Mv;  Eq |= hm;  Xh = (((Eq & Pv) + Pv) ^ Pv) | Eq
-                    //   Ph = Mv | ~(Xh | Pv);  Mh = Pv & Xh   (out: their bit 63)
-                    //   Ph = Ph << 1 | hp;  Mh = Mh << 1 | hm
-                    //   Pv = Mh | ~(Xv | Ph);  Mv = Ph & Xv
-                    // Block 0 runs for every lane here (L > 0 whenever a column runs).
-                    uint32_t hp = 0, hm = 0;
-#pragma unroll
-                    for (int w = 0; w < W; ++w) {
-                        if (w == 0 || w < wu) {
-                            uint32_t el = (uint32_t)eqw[w];
-                            const uint32_t eh = (uint32_t)(eqw[w] >> 32);
-                            const uint32_t xvl = el | mvl[w], xvh = eh | mvh[w];
-                            el |= hm;
-                            // (Eq & Pv) + Pv over the 64 rows: low half, carry, high half
-                            const uint32_t tl = el & pvl[w];
-                            const uint32_t sl = tl + pvl[w];
-                            const uint32_t sh = (eh & pvh[w]) + pvh[w] + (sl < tl ? 1u : 0u);
-                            const uint32_t xhl = bitop3<kXorOr>(sl, pvl[w], el);
-                            const uint32_t xhh = bitop3<kXorOr>(sh, pvh[w], eh);
-                            uint32_t phl = bitop3<kOrNor>(mvl[w], xhl, pvl[w]);
-                            uint32_t phh = bitop3<kOrNor>(mvh[w], xhh, pvh[w]);
-                            uint32_t mhl = pvl[w] & xhl, mhh = pvh[w] & xhh;
-                            const uint32_t hp_out = phh >> 31;
-                            const uint32_t hm_out = mhh >> 31;
-                            phh = __builtin_amdgcn_alignbit(phh, phl, 31);
-                            phl = (phl << 1) | hp;
-                            mhh = __builtin_amdgcn_alignbit(mhh, mhl, 31);
-                            mhl = (mhl << 1) | hm;
-                            pvl[w] = bitop3<kOrNor>(mhl, xvl, phl);
-                            pvh[w] = bitop3<kOrNor>(mhh, xvh, phh);
-                            mvl[w] = phl & xvl;
-                            mvh[w] = phh & xvh;
-                            hp = hp_out;
-                            hm = hm_out;
-                        }
-                    }
-                    score += (int32_t)hp - (int32_t)hm;
-                    best = min(best, score);
-                }
+                const int32_t best = column_scan_from<NW, 0>(NW - nmax, peq + t, pv, mv, rp,
+                                                             rp_words, wsh, span, (int32_t)L);
                 d = min<int32_t>(best, (int32_t)E + 1);
                 ok = best <= (int32_t)E;
             }
