@@ -798,12 +798,7 @@ extern "C" int grim_verify_survivors(const grim_index_t *idx, const grim_batch_t
     a.n_surv = n_survivors;
     a.dist = dist;
     a.ok_bits = ok_bits;
-    const uint64_t waves = (n_survivors + 63) / 64;
-    uint64_t grid = (waves + 3) / 4;
-    const uint64_t cap = (uint64_t)cu_count(idx->device) * 16;
-    if (grid > cap)
-        grid = cap;
-    HIP_TRY(launch_verify(reinterpret_cast<hipStream_t>(stream), W, (uint32_t)grid, a));
+    HIP_TRY(launch_verify(reinterpret_cast<hipStream_t>(stream), W, cu_count(idx->device), a));
     return GRIM_OK;
 }
 

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
+
 #include "grim_internal.h"
 
 namespace grim {
@@ -363,153 +365,197 @@ __device__ __forceinline__ int32_t column_scan_from(int s, const uint64_t *peq_t
     return column_scan<NW, S>(peq_t, pv, mv, rp, rp_words, wsh, span, L);
 }
 
-// A workgroup takes 256 survivors at a time and hands them to its threads
-// sorted by the number of 32-row words of their read (counting sort in LDS),
-// so that most wavefronts hold reads of one length class; pass bits of the
-// 256 are gathered in LDS and stored as 8 whole words.  W is the number of
-// 64-row blocks (NW = 2 W words) the batch's longest read needs.
+// Each workgroup owns one contiguous range of survivors (the ranges are of
+// equal size and start on multiples of 32, so that no two workgroups share a
+// word of pass bits; the grid is what the GPU holds at once).  It takes its
+// range 1024 survivors at a time, sorts them by the number of 32-row words of
+// their read (counting sort in LDS; survivors with nothing to align first,
+// empty slots of a short last chunk last) and runs the sorted list in four
+// rounds of 256, thread t taking sorted slot 256 r + t: a wavefront's 64
+// lanes then mostly hold reads of one length class, and every wavefront
+// meets short and long reads over the four rounds, so none waits long for
+// the others at the chunk's end.  Pass bits of the chunk are gathered in LDS
+// and stored as whole words.  W is the number of 64-row blocks (NW = 2 W
+// words) the batch's longest read needs.
+constexpr int kVerifyChunk = 1024;
+
 template <int W>
 __global__ __launch_bounds__(256) void verify_kernel(VerifyArgs a)
 {
     constexpr int NW = 2 * W;
-    __shared__ uint32_t order[256];
-    __shared__ uint32_t cls[NW + 1];
-    __shared__ uint32_t okw[8];
+    constexpr int CH = kVerifyChunk;
+    __shared__ uint16_t order[CH];
+    __shared__ uint32_t cls[NW + 2];
+    __shared__ uint32_t okw[CH / 32];
     // match masks of every thread's read: peq[(base * W + block) * 256 + thread],
     // block = rows 64 block .. 64 block + 63 of the bottom-aligned vector
     // (lane-interleaved, so that a wavefront's reads of one column are
     // conflict-free whatever bases its lanes see)
     __shared__ uint64_t peq[4 * W * 256];
     const int t = threadIdx.x;
-    const uint64_t stride = (uint64_t)gridDim.x * 256;
-    const uint64_t n_words = (a.n_surv + 31) / 32;
-    for (uint64_t base = (uint64_t)blockIdx.x * 256; base < a.n_surv; base += stride) {
-        // word count of survivor base + t (0 when there is nothing to align)
-        int key = 0;
-        {
-            const uint64_t i = base + t;
-            if (i < a.n_surv) {
-                const uint32_t r = a.surv_read[i];
-                if (r < a.n_reads) {
-                    const uint32_t L = a.read_len[r];
-                    key = L <= 32u * NW ? (int)((L + 31) >> 5) : 0;
-                }
-            }
-        }
-        if (t <= NW)
+    const uint64_t per = ((a.n_surv + gridDim.x - 1) / gridDim.x + 31) & ~31ull;
+    const uint64_t g0 = (uint64_t)blockIdx.x * per;
+    const uint64_t g1 = g0 + per < a.n_surv ? g0 + per : a.n_surv;
+    for (uint64_t base = g0; base < g1; base += CH) {
+        const uint32_t cnt = (uint32_t)(g1 - base < (uint64_t)CH ? g1 - base : CH);
+        if (t < NW + 2)
             cls[t] = 0;
-        if (t < 8)
+        if (t < CH / 32)
             okw[t] = 0;
         __syncthreads();
-        const uint32_t rank = atomicAdd(&cls[key], 1u);
-        __syncthreads();
-        uint32_t start = 0;
-        for (int c = 0; c < key; ++c)
-            start += cls[c];
-        order[start + rank] = (uint32_t)t;
-        __syncthreads();
-        const uint32_t slot = order[t];
-        const uint64_t i = base + slot;
-        if (i < a.n_surv) {
-            int32_t d = -1;
-            bool ok = false;
-            const uint32_t r = a.surv_read[i], b = a.surv_bin[i];
-            const uint64_t nb = a.nw * 16;
-            const uint32_t L = r < a.n_reads ? a.read_len[r] : 0u;
-            const uint64_t off = r < a.n_reads ? a.read_off[r] : 0u;
-            if (r < a.n_reads && b < a.n_bins && L <= 32u * NW && off <= nb && L <= nb - off) {
-                const uint32_t E =
-                    (uint32_t)(((uint64_t)a.read_e[r] * L + a.e_den - 1) / a.e_den);
-                const int pad = 32 * NW - (int)L;   // rows above the read
-                uint32_t pv[NW], mv[NW];
+        // class of slot u 256 + t: its read's word count, 0 when there is
+        // nothing to align, NW + 1 past the chunk's end
+        int key[CH / 256];
+        uint32_t rank[CH / 256];
 #pragma unroll
-                for (int w = 0; w < W; ++w) {
-                    // 16 rows at a time: rows 64 w + 16 g + k (k = 0..15) hold
-                    // read bases i0 + k, i0 = 64 w + 16 g - pad; rows with
-                    // i0 + k < 0 match every base
-                    uint32_t ma[2] = {0u, 0u}, mc[2] = {0u, 0u}, mg[2] = {0u, 0u},
-                             mt[2] = {0u, 0u}, pw[2] = {~0u, ~0u};
-#pragma unroll
-                    for (int g = 0; g < 4; ++g) {
-                        const int i0 = 64 * w + 16 * g - pad;
-                        const uint32_t sh = 16 * (g & 1);
-                        const int half = g >> 1;
-                        uint32_t xa = 0xFFFFu, xc = 0xFFFFu, xg = 0xFFFFu, xt = 0xFFFFu,
-                                 pm = 0xFFFFu;
-                        if (i0 > -16) {
-                            pm = i0 >= 0 ? 0u : (1u << -i0) - 1u;
-                            // base k in bits 2k (high bit of its code) and 2k + 1 (low bit)
-                            const uint32_t rv = __builtin_bitreverse32(
-                                read_window(a.rw, a.nw, (int64_t)off + i0));
-                            const uint32_t h = rv & 0x55555555u, l = (rv >> 1) & 0x55555555u;
-                            xa = even_bits(~(h | l) & 0x55555555u) | pm;
-                            xc = even_bits(l & ~h) | pm;
-                            xg = even_bits(h & ~l) | pm;
-                            xt = even_bits(h & l) | pm;
-                        }
-                        ma[half] |= xa << sh;
-                        mc[half] |= xc << sh;
-                        mg[half] |= xg << sh;
-                        mt[half] |= xt << sh;
-                        pw[half] &= ~(pm << sh);
-                    }
-                    peq[(0 * W + w) * 256 + t] = (uint64_t)ma[1] << 32 | ma[0];
-                    peq[(1 * W + w) * 256 + t] = (uint64_t)mc[1] << 32 | mc[0];
-                    peq[(2 * W + w) * 256 + t] = (uint64_t)mg[1] << 32 | mg[0];
-                    peq[(3 * W + w) * 256 + t] = (uint64_t)mt[1] << 32 | mt[0];
-                    pv[2 * w] = pw[0];
-                    pv[2 * w + 1] = pw[1];
-                    mv[2 * w] = mv[2 * w + 1] = 0u;
+        for (int u = 0; u < CH / 256; ++u) {
+            const uint32_t p = u * 256 + t;
+            int k = NW + 1;
+            if (p < cnt) {
+                k = 0;
+                const uint32_t r = a.surv_read[base + p];
+                if (r < a.n_reads) {
+                    const uint32_t L = a.read_len[r];
+                    k = L <= 32u * NW ? (int)((L + 31) >> 5) : 0;
                 }
-                const uint64_t lo = (uint64_t)b * a.B;
-                uint64_t hi = lo + a.B + a.O;
-                if (hi > a.G)
-                    hi = a.G;
-                // an empty read matches anywhere with no edits: no columns
-                const uint64_t span = hi > lo && L > 0 ? hi - lo : 0;
-                // the wavefront's first word: the most words any of its
-                // scanning lanes needs, counted from the bottom
-                const uint32_t n = (L + 31) >> 5;
-                int nmax = 0;
-#pragma unroll
-                for (int v = 1; v <= NW; ++v)
-                    nmax += __builtin_amdgcn_ballot_w64(n >= (uint32_t)v) != 0;
-                // 16 reference bases are fetched every 16 columns; their bit
-                // offset inside the first packed word is the span start's,
-                // the same at every fetch.  The first word is in bounds since
-                // lo + j < hi <= G.
-                const uint32_t *rp = a.ref + (lo >> 4);
-                const uint64_t rp_words = a.ref_words - (lo >> 4);
-                const uint32_t wsh = ((uint32_t)lo & 15u) << 1;
-                const int32_t best = column_scan_from<NW, 0>(NW - nmax, peq + t, pv, mv, rp,
-                                                             rp_words, wsh, span, (int32_t)L);
-                d = min<int32_t>(best, (int32_t)E + 1);
-                ok = best <= (int32_t)E;
             }
-            a.dist[i] = d;
-            if (ok)
-                atomicOr(&okw[slot >> 5], 1u << (slot & 31));
+            key[u] = k;
+            rank[u] = atomicAdd(&cls[k], 1u);
         }
         __syncthreads();
-        if (t < 8 && (base >> 5) + t < n_words)
+#pragma unroll
+        for (int u = 0; u < CH / 256; ++u) {
+            uint32_t start = 0;
+            for (int c = 0; c < key[u]; ++c)
+                start += cls[c];
+            order[start + rank[u]] = (uint16_t)(u * 256 + t);
+        }
+        __syncthreads();
+        for (int round = 0; round < CH / 256; ++round) {
+            const uint32_t slot = order[round * 256 + t];
+            const uint64_t i = base + slot;
+            if (slot < cnt) {
+                int32_t d = -1;
+                bool ok = false;
+                const uint32_t r = a.surv_read[i], b = a.surv_bin[i];
+                const uint64_t nb = a.nw * 16;
+                const uint32_t L = r < a.n_reads ? a.read_len[r] : 0u;
+                const uint64_t off = r < a.n_reads ? a.read_off[r] : 0u;
+                if (r < a.n_reads && b < a.n_bins && L <= 32u * NW && off <= nb &&
+                    L <= nb - off) {
+                    const uint32_t E =
+                        (uint32_t)(((uint64_t)a.read_e[r] * L + a.e_den - 1) / a.e_den);
+                    const int pad = 32 * NW - (int)L;   // rows above the read
+                    uint32_t pv[NW], mv[NW];
+#pragma unroll
+                    for (int w = 0; w < W; ++w) {
+                        // 16 rows at a time: rows 64 w + 16 g + k (k = 0..15) hold
+                        // read bases i0 + k, i0 = 64 w + 16 g - pad; rows with
+                        // i0 + k < 0 match every base
+                        uint32_t ma[2] = {0u, 0u}, mc[2] = {0u, 0u}, mg[2] = {0u, 0u},
+                                 mt[2] = {0u, 0u}, pw[2] = {~0u, ~0u};
+#pragma unroll
+                        for (int g = 0; g < 4; ++g) {
+                            const int i0 = 64 * w + 16 * g - pad;
+                            const uint32_t sh = 16 * (g & 1);
+                            const int half = g >> 1;
+                            uint32_t xa = 0xFFFFu, xc = 0xFFFFu, xg = 0xFFFFu, xt = 0xFFFFu,
+                                     pm = 0xFFFFu;
+                            if (i0 > -16) {
+                                pm = i0 >= 0 ? 0u : (1u << -i0) - 1u;
+                                // base k in bits 2k (high bit of its code) and 2k + 1 (low bit)
+                                const uint32_t rv = __builtin_bitreverse32(
+                                    read_window(a.rw, a.nw, (int64_t)off + i0));
+                                const uint32_t h = rv & 0x55555555u, l = (rv >> 1) & 0x55555555u;
+                                xa = even_bits(~(h | l) & 0x55555555u) | pm;
+                                xc = even_bits(l & ~h) | pm;
+                                xg = even_bits(h & ~l) | pm;
+                                xt = even_bits(h & l) | pm;
+                            }
+                            ma[half] |= xa << sh;
+                            mc[half] |= xc << sh;
+                            mg[half] |= xg << sh;
+                            mt[half] |= xt << sh;
+                            pw[half] &= ~(pm << sh);
+                        }
+                        peq[(0 * W + w) * 256 + t] = (uint64_t)ma[1] << 32 | ma[0];
+                        peq[(1 * W + w) * 256 + t] = (uint64_t)mc[1] << 32 | mc[0];
+                        peq[(2 * W + w) * 256 + t] = (uint64_t)mg[1] << 32 | mg[0];
+                        peq[(3 * W + w) * 256 + t] = (uint64_t)mt[1] << 32 | mt[0];
+                        pv[2 * w] = pw[0];
+                        pv[2 * w + 1] = pw[1];
+                        mv[2 * w] = mv[2 * w + 1] = 0u;
+                    }
+                    const uint64_t lo = (uint64_t)b * a.B;
+                    uint64_t hi = lo + a.B + a.O;
+                    if (hi > a.G)
+                        hi = a.G;
+                    // an empty read matches anywhere with no edits: no columns
+                    const uint64_t span = hi > lo && L > 0 ? hi - lo : 0;
+                    // the wavefront's first word: the most words any of its
+                    // scanning lanes needs, counted from the bottom
+                    const uint32_t n = (L + 31) >> 5;
+                    int nmax = 0;
+#pragma unroll
+                    for (int v = 1; v <= NW; ++v)
+                        nmax += __builtin_amdgcn_ballot_w64(n >= (uint32_t)v) != 0;
+                    // 16 reference bases are fetched every 16 columns; their bit
+                    // offset inside the first packed word is the span start's,
+                    // the same at every fetch.  The first word is in bounds since
+                    // lo + j < hi <= G.
+                    const uint32_t *rp = a.ref + (lo >> 4);
+                    const uint64_t rp_words = a.ref_words - (lo >> 4);
+                    const uint32_t wsh = ((uint32_t)lo & 15u) << 1;
+                    const int32_t best = column_scan_from<NW, 0>(NW - nmax, peq + t, pv, mv, rp,
+                                                                 rp_words, wsh, span, (int32_t)L);
+                    d = min<int32_t>(best, (int32_t)E + 1);
+                    ok = best <= (int32_t)E;
+                }
+                a.dist[i] = d;
+                if (ok)
+                    atomicOr(&okw[slot >> 5], 1u << (slot & 31));
+            }
+        }
+        __syncthreads();
+        if (t < (int)((cnt + 31) / 32))
             a.ok_bits[(base >> 5) + t] = okw[t];
         __syncthreads();
     }
 }
 
-hipError_t launch_verify(hipStream_t s, int W, uint32_t grid, const VerifyArgs &a)
+hipError_t launch_verify(hipStream_t s, int W, int cus, const VerifyArgs &a)
 {
     VerifyArgs copy = a;
     void *args[] = {&copy};
     const void *k = nullptr;
+    int wi = 0;
     switch (W) {
-    case 1: k = reinterpret_cast<const void *>(&verify_kernel<1>); break;
-    case 2: k = reinterpret_cast<const void *>(&verify_kernel<2>); break;
-    case 4: k = reinterpret_cast<const void *>(&verify_kernel<4>); break;
-    case 8: k = reinterpret_cast<const void *>(&verify_kernel<8>); break;
+    case 1: k = reinterpret_cast<const void *>(&verify_kernel<1>); wi = 0; break;
+    case 2: k = reinterpret_cast<const void *>(&verify_kernel<2>); wi = 1; break;
+    case 4: k = reinterpret_cast<const void *>(&verify_kernel<4>); wi = 2; break;
+    case 8: k = reinterpret_cast<const void *>(&verify_kernel<8>); wi = 3; break;
     default: return hipErrorInvalidValue;
     }
-    return hipLaunchKernel(k, dim3(grid), dim3(256), args, 0, s);
+    // workgroups resident per CU (LDS bound), asked once per kernel
+    static std::atomic<int> resident[4];
+    int per_cu = resident[wi].load(std::memory_order_relaxed);
+    if (per_cu <= 0) {
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 256, 0);
+        if (e != hipSuccess)
+            return e;
+        if (per_cu <= 0)
+            per_cu = 1;
+        resident[wi].store(per_cu, std::memory_order_relaxed);
+    }
+    // one sorted chunk per workgroup, dispatched as resident ones finish;
+    // past 64 times the resident count, each takes a run of m whole chunks
+    const uint64_t chunks = (a.n_surv + kVerifyChunk - 1) / kVerifyChunk;
+    const uint64_t cap = (uint64_t)per_cu * (uint64_t)(cus > 0 ? cus : 1) * 64;
+    const uint64_t m = (chunks + cap - 1) / cap;
+    const uint64_t grid = (chunks + m - 1) / m;
+    if (grid == 0)
+        return hipSuccess;
+    return hipLaunchKernel(k, dim3((uint32_t)grid), dim3(256), args, 0, s);
 }
 
 }  // namespace grim

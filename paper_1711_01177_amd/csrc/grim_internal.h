@@ -102,7 +102,7 @@ hipError_t launch_compact(hipStream_t s, const uint32_t *bits, uint64_t n_pairs,
                           uint64_t cap, uint64_t *surv_pair, uint32_t *surv_read,
                           uint32_t *surv_bin, uint64_t *n_out, uint64_t *block_sums);
 uint64_t compact_blocks(uint64_t n_pairs);
-hipError_t launch_verify(hipStream_t s, int W, uint32_t grid, const VerifyArgs &a);
+hipError_t launch_verify(hipStream_t s, int W, int cus, const VerifyArgs &a);
 hipError_t launch_transpose(hipStream_t s, int q, const uint32_t *vec, uint64_t n_bins,
                             uint64_t row_words, uint32_t *rows, uint32_t grid);
 // Persistent grid: as many workgroups as fit on the device's cus compute units

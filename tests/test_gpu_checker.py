@@ -187,3 +187,63 @@ def test_verify_edges():
     with pytest.raises(g.GrimError) as ex:
         _verify_gpu(g, idx, w, surv_read, surv_bin, max_len=600)
     assert ex.value.code == g.GRIM_E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("n_surv", [2_500_037, 70_000_037])
+def test_verify_many_chunks(n_surv):
+    """Long survivor lists for the alignment check: 2.5M (plus 37) survivors
+    give some 2,400 sorted chunks of 1024, one per workgroup, and a ragged
+    last one; 70M (plus 37) exceed 64 times the resident workgroups, so that
+    each workgroup takes a run of chunks.  Survivors are drawn from 40,000
+    distinct read/bin pairs so that the oracle runs once per distinct pair;
+    read lengths 0-200 mixed at random, a few read ids and bin ids out of
+    range (distance -1, not verified), every distance and pass bit compared."""
+    import torch
+    g = lib()
+    rng = np.random.default_rng(77)
+    ref = gs.reference(21, 200_000, 0.3, 5, 200, 0.85, 0.98)
+    q, B, O = 4, 8, 4
+    nb = (ref.size + B - 1) // B
+    n_reads = 4000
+    reads, cands, es, origin = [], [], [], []
+    for _ in range(n_reads):
+        L = int(rng.integers(0, 201))
+        st = int(rng.integers(0, ref.size - L))
+        origin.append(st)
+        r = ref[st:st + L].copy()
+        for _ in range(int(rng.integers(0, 4))):
+            if L:
+                r[int(rng.integers(0, L))] = int(rng.integers(0, 4))
+        reads.append(r)
+        cands.append([])
+        es.append(int(rng.choice([0, 500, 1000, 2500])))
+    w = custom_workload(ref, q, B, O, reads, cands, es)
+    n_pairs = 40_000
+    pr = rng.integers(0, n_reads, n_pairs).astype(np.uint32)
+    pb = rng.integers(0, nb, n_pairs).astype(np.uint32)
+    # a third of the pairs at the read's own bin, so that many verify
+    near = rng.random(n_pairs) < 1 / 3
+    pb[near] = np.array(origin, dtype=np.int64)[pr[near]] // B
+    want_pair = oracle.verify(ref, B, O, w["codes"], w["read_off"], w["read_len"], w["read_e"],
+                              w["e_den"], pr, pb)
+    k = rng.integers(0, n_pairs, n_surv, dtype=np.int32)
+    sr = pr[k].copy()
+    sb = pb[k].copy()
+    want = want_pair[k].copy()
+    bad_r = rng.choice(n_surv, 50, replace=False)
+    bad_b = rng.choice(n_surv, 50, replace=False)
+    sr[bad_r] = n_reads + 5
+    sb[bad_b] = nb + 1
+    want[bad_r] = -1
+    want[bad_b] = -1
+    idx = g.grim_build_bins(ref, q, B, O)
+    idx.attach_reference(ref)
+    dist, okb = _verify_gpu(g, idx, w, sr, sb, max_len=256)
+    assert np.array_equal(dist, want), np.nonzero(dist != want)[0][:5]
+    E = ((w["read_e"].astype(np.int64) * w["read_len"] + w["e_den"] - 1) // w["e_den"])
+    E = np.append(E, 0).astype(np.int32)   # index n_reads: the out-of-range read ids
+    want_ok = (want >= 0) & (want <= E[np.minimum(sr, n_reads)])
+    okn = np.unpackbits(okb.view(np.uint8), bitorder="little")[:n_surv]
+    assert np.array_equal(okn.astype(bool), want_ok)
+    assert okb.size == (n_surv + 31) // 32
+    assert okb[-1] >> (n_surv & 31) == 0
