@@ -365,18 +365,19 @@ __device__ __forceinline__ int32_t column_scan_from(int s, const uint64_t *peq_t
     return column_scan<NW, S>(peq_t, pv, mv, rp, rp_words, wsh, span, L);
 }
 
-// Each workgroup owns one contiguous range of survivors (the ranges are of
-// equal size and start on multiples of 32, so that no two workgroups share a
-// word of pass bits; the grid is what the GPU holds at once).  It takes its
-// range 1024 survivors at a time, sorts them by the number of 32-row words of
-// their read (counting sort in LDS; survivors with nothing to align first,
-// empty slots of a short last chunk last) and runs the sorted list in four
-// rounds of 256, thread t taking sorted slot 256 r + t: a wavefront's 64
-// lanes then mostly hold reads of one length class, and every wavefront
-// meets short and long reads over the four rounds, so none waits long for
-// the others at the chunk's end.  Pass bits of the chunk are gathered in LDS
-// and stored as whole words.  W is the number of 64-row blocks (NW = 2 W
-// words) the batch's longest read needs.
+// Each workgroup owns one contiguous range of survivors: one chunk of 1024,
+// or a run of whole chunks once the list exceeds 64 times the workgroups the
+// GPU holds at once (ranges start on multiples of 32, so that no two
+// workgroups share a word of pass bits).  It takes its range 1024 survivors
+// at a time, sorts them by the number of 32-row words of their read
+// (counting sort in LDS; survivors with nothing to align first, empty slots
+// of a short last chunk last) and runs the sorted list in four rounds of
+// 256, thread t taking sorted slot 256 r + t: a wavefront's 64 lanes then
+// mostly hold reads of one length class, and every wavefront meets short and
+// long reads over the four rounds, so none waits long for the others at the
+// chunk's end.  Pass bits of the chunk are gathered in LDS and stored as
+// whole words.  W is the number of 64-row blocks (NW = 2 W words) the
+// batch's longest read needs.
 constexpr int kVerifyChunk = 1024;
 
 template <int W>
