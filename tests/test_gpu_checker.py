@@ -189,15 +189,18 @@ def test_verify_edges():
     assert ex.value.code == g.GRIM_E_UNSUPPORTED
 
 
-@pytest.mark.parametrize("n_surv", [2_500_037, 70_000_037])
-def test_verify_many_chunks(n_surv):
+@pytest.mark.parametrize("n_surv,max_len", [(2_500_037, 256), (70_000_037, 256),
+                                            (2_500_037, 512)])
+def test_verify_many_chunks(n_surv, max_len):
     """Long survivor lists for the alignment check: 2.5M (plus 37) survivors
     give some 2,400 sorted chunks of 1024, one per workgroup, and a ragged
     last one; 70M (plus 37) exceed 64 times the resident workgroups, so that
     each workgroup takes a run of chunks.  Survivors are drawn from 40,000
     distinct read/bin pairs so that the oracle runs once per distinct pair;
     read lengths 0-200 mixed at random, a few read ids and bin ids out of
-    range (distance -1, not verified), every distance and pass bit compared."""
+    range (distance -1, not verified), every distance and pass bit compared.
+    With max_len 512 the reads are 0-400 bases and the 8-block kernel runs
+    (its column scan compiled for each of 16 first words)."""
     import torch
     g = lib()
     rng = np.random.default_rng(77)
@@ -207,7 +210,7 @@ def test_verify_many_chunks(n_surv):
     n_reads = 4000
     reads, cands, es, origin = [], [], [], []
     for _ in range(n_reads):
-        L = int(rng.integers(0, 201))
+        L = int(rng.integers(0, 201 if max_len == 256 else 401))
         st = int(rng.integers(0, ref.size - L))
         origin.append(st)
         r = ref[st:st + L].copy()
@@ -238,7 +241,7 @@ def test_verify_many_chunks(n_surv):
     want[bad_b] = -1
     idx = g.grim_build_bins(ref, q, B, O)
     idx.attach_reference(ref)
-    dist, okb = _verify_gpu(g, idx, w, sr, sb, max_len=256)
+    dist, okb = _verify_gpu(g, idx, w, sr, sb, max_len=max_len)
     assert np.array_equal(dist, want), np.nonzero(dist != want)[0][:5]
     E = ((w["read_e"].astype(np.int64) * w["read_len"] + w["e_den"] - 1) // w["e_den"])
     E = np.append(E, 0).astype(np.int32)   # index n_reads: the out-of-range read ids
