@@ -537,7 +537,8 @@ hipError_t launch_verify(hipStream_t s, int W, int cus, const VerifyArgs &a)
     case 8: k = reinterpret_cast<const void *>(&verify_kernel<8>); wi = 3; break;
     default: return hipErrorInvalidValue;
     }
-    // workgroups resident per CU (LDS bound), asked once per kernel
+    // workgroups resident per CU (LDS bound), asked once per kernel and
+    // process; it only sizes the grid's cap, never what is computed
     static std::atomic<int> resident[4];
     int per_cu = resident[wi].load(std::memory_order_relaxed);
     if (per_cu <= 0) {
