@@ -250,3 +250,35 @@ def test_verify_many_chunks(n_surv, max_len):
     assert np.array_equal(okn.astype(bool), want_ok)
     assert okb.size == (n_surv + 31) // 32
     assert okb[-1] >> (n_surv & 31) == 0
+
+
+@pytest.mark.parametrize("G", [1, 5, 15, 16, 17, 33, 40])
+def test_verify_tiny_references(G):
+    """References of one to three packed words: every bin's span ends at the
+    reference's end, so the alignment check's look-ahead fetches of reference
+    words past the end are all clamped.  Reads of 0-70 bases (some longer
+    than the reference), every bin, two strides, against the oracle."""
+    g = lib()
+    rng = np.random.default_rng(300 + G)
+    ref = rng.integers(0, 4, G).astype(np.uint8)
+    for B, O in ((4, 3), (16, 20)):
+        q = 4
+        nb = (G + B - 1) // B
+        reads, cands = [], []
+        for L in (0, 1, 3, 4, 9, 16, 31, 32, 33, 64, 70):
+            r = rng.integers(0, 4, L).astype(np.uint8)
+            if 0 < L <= G:                       # some reads copied from the reference
+                st = int(rng.integers(0, G - L + 1))
+                r = ref[st:st + L].copy()
+            reads.append(r)
+            cands.append(list(range(nb)))
+        w = custom_workload(ref, q, B, O, reads, cands, [500] * len(reads))
+        idx = g.grim_build_bins(ref, q, B, O)
+        idx.attach_reference(ref)
+        off = w["cand_off"].astype(np.int64)
+        sr = np.repeat(np.arange(len(reads), dtype=np.uint32), np.diff(off))
+        sb = w["cand_bin"].copy()
+        dist, _ = _verify_gpu(g, idx, w, sr, sb, max_len=128)
+        want = oracle.verify(ref, B, O, w["codes"], w["read_off"], w["read_len"], w["read_e"],
+                             w["e_den"], sr, sb)
+        assert np.array_equal(dist, want), (G, B, O, dist, want)
