@@ -743,10 +743,12 @@ extern "C" int grim_index_attach_reference(grim_index_t *idx, const uint32_t *re
         return GRIM_E_INVALID;
     const uint64_t nw = grim_packed_words(ref_len);
     uint32_t *d = nullptr;
-    if (hipMalloc(&d, nw * 4) != hipSuccess)
+    if (hipMalloc(&d, (nw + kRefPadWords) * 4) != hipSuccess)
         return GRIM_E_NOMEM;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     hipError_t e = hipMemcpyAsync(d, ref_2bit, nw * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = launch_zero(s, d + nw, kRefPadWords);
     if (e == hipSuccess)
         e = hipStreamSynchronize(s);
     if (e != hipSuccess) {

@@ -280,7 +280,7 @@ constexpr uint32_t kOrNor = (0xF0u | ~(0xCCu | 0xAAu)) & 0xFFu;  // a | ~(b | c)
 
 // The column scan over words S..NW-1 of every lane (S is the same for the
 // whole wavefront).  peq_t points at this thread's match masks (64-bit pairs
-// of words, base-major, 256 threads apart); rp/rp_words/wsh locate the span
+// of words, base-major, 256 threads apart); rp/wsh locate the span
 // in the packed reference.  Returns the smallest distance at the read's last
 // row over the span's columns (L when the span is empty).  Per column and
 // word, with Pv/Mv the vertical deltas and c the carry of the addition:
@@ -289,24 +289,32 @@ constexpr uint32_t kOrNor = (0xF0u | ~(0xCCu | 0xAAu)) & 0xFFu;  // a | ~(b | c)
 //   Ph, Mh shifted up one row (bit 31 of the word below comes in; 0 at S)
 //   Pv = Mh | ~(Xv | Ph);  Mv = Ph & Xv
 // and the distance at the last row moves by bit 31 of Ph minus that of Mh.
-template <int NW, int S>
+// UNI: every lane of the wavefront that runs the scan has the same span, so
+// the column loop's trip count is uniform (kept in scalar registers).
+template <int NW, int S, bool UNI>
 __device__ __forceinline__ int32_t column_scan(const uint64_t *peq_t, uint32_t (&pv)[NW],
                                                uint32_t (&mv)[NW], const uint32_t *rp,
-                                               uint64_t rp_words, uint32_t wsh, uint64_t span,
-                                               int32_t L)
+                                               uint32_t wsh, uint64_t span, int32_t L)
 {
     int32_t score = L, best = L;
+    if (UNI)
+        span = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(span >> 32)) << 32) |
+               __builtin_amdgcn_readfirstlane((uint32_t)span);
     if (span == 0)
         return best;
     // Loads run ahead of their use: the two reference words of the next
     // 16-column fetch one fetch ahead, and each pair of mask words of the
     // next column as soon as the current column is done with that pair.
-    // Word k of a fetch that is used is in bounds (the columns lie below G);
-    // indexes past the end are clamped (those bases are never used), so the
-    // loads are unconditional and nothing waits on them before their use.
-    const uint64_t last = rp_words - 1;
-    uint32_t win = (uint32_t)(((uint64_t)rp[0] << 32 | rp[1 < last ? 1 : last]) >> (32 - wsh));
-    uint64_t nxt = (uint64_t)rp[1 < last ? 1 : last] << 32 | rp[2 < last ? 2 : last];
+    // The fetches reach at most three words past the reference's last one;
+    // the reference is followed by zero words there (those bases are never
+    // used), so the loads are unconditional and nothing waits on them before
+    // their use.
+    // nxt holds the next fetch's two words in memory order (first word in the
+    // low half); they swap halves only where used, so that nothing waits on
+    // the load before then
+    uint32_t win = (uint32_t)(((uint64_t)rp[0] << 32 | rp[1]) >> (32 - wsh));
+    uint64_t nxt;
+    __builtin_memcpy(&nxt, rp + 1, 8);
     uint64_t e2[NW / 2];
     {
         const uint64_t *pq = peq_t + __builtin_amdgcn_ubfe(win, 30, 2) * (NW / 2 * 256);
@@ -318,9 +326,8 @@ __device__ __forceinline__ int32_t column_scan(const uint64_t *peq_t, uint32_t (
         // the next column's base (the 16-base window moves on after column 15)
         const uint32_t col = (uint32_t)j & 15;
         if (col == 15) {
-            win = (uint32_t)(nxt >> (32 - wsh));
-            const uint64_t k = (j >> 4) + 2;
-            nxt = (uint64_t)rp[k < last ? k : last] << 32 | rp[k + 1 < last ? k + 1 : last];
+            win = (uint32_t)(((nxt << 32) | (nxt >> 32)) >> (32 - wsh));
+            __builtin_memcpy(&nxt, rp + (j >> 4) + 2, 8);
         }
         const uint32_t cbn = __builtin_amdgcn_ubfe(win, 30 - 2 * ((col + 1) & 15), 2);
         const uint64_t *pqn = peq_t + cbn * (NW / 2 * 256);
@@ -352,17 +359,17 @@ __device__ __forceinline__ int32_t column_scan(const uint64_t *peq_t, uint32_t (
 }
 
 // Picks the scan for the wavefront's first word s (uniform across it).
-template <int NW, int S>
+template <int NW, int S, bool UNI>
 __device__ __forceinline__ int32_t column_scan_from(int s, const uint64_t *peq_t,
                                                     uint32_t (&pv)[NW], uint32_t (&mv)[NW],
-                                                    const uint32_t *rp, uint64_t rp_words,
-                                                    uint32_t wsh, uint64_t span, int32_t L)
+                                                    const uint32_t *rp, uint32_t wsh,
+                                                    uint64_t span, int32_t L)
 {
     if constexpr (S + 1 < NW) {
         if (s != S)
-            return column_scan_from<NW, S + 1>(s, peq_t, pv, mv, rp, rp_words, wsh, span, L);
+            return column_scan_from<NW, S + 1, UNI>(s, peq_t, pv, mv, rp, wsh, span, L);
     }
-    return column_scan<NW, S>(peq_t, pv, mv, rp, rp_words, wsh, span, L);
+    return column_scan<NW, S, UNI>(peq_t, pv, mv, rp, wsh, span, L);
 }
 
 // Each workgroup owns one contiguous range of survivors: one chunk of 1024,
@@ -502,13 +509,19 @@ __global__ __launch_bounds__(256) void verify_kernel(VerifyArgs a)
                         nmax += __builtin_amdgcn_ballot_w64(n >= (uint32_t)v) != 0;
                     // 16 reference bases are fetched every 16 columns; their bit
                     // offset inside the first packed word is the span start's,
-                    // the same at every fetch.  The first word is in bounds since
-                    // lo + j < hi <= G.
+                    // the same at every fetch.
                     const uint32_t *rp = a.ref + (lo >> 4);
-                    const uint64_t rp_words = a.ref_words - (lo >> 4);
                     const uint32_t wsh = ((uint32_t)lo & 15u) << 1;
-                    const int32_t best = column_scan_from<NW, 0>(NW - nmax, peq + t, pv, mv, rp,
-                                                                 rp_words, wsh, span, (int32_t)L);
+                    // one span for all scanning lanes (all but the last bin's)?
+                    const uint32_t s_lo = __builtin_amdgcn_readfirstlane((uint32_t)span);
+                    const uint32_t s_hi = __builtin_amdgcn_readfirstlane((uint32_t)(span >> 32));
+                    const bool uni = __builtin_amdgcn_ballot_w64(
+                                         span != ((uint64_t)s_hi << 32 | s_lo)) == 0;
+                    const int32_t best =
+                        uni ? column_scan_from<NW, 0, true>(NW - nmax, peq + t, pv, mv, rp, wsh,
+                                                            span, (int32_t)L)
+                            : column_scan_from<NW, 0, false>(NW - nmax, peq + t, pv, mv, rp,
+                                                             wsh, span, (int32_t)L);
                     d = min<int32_t>(best, (int32_t)E + 1);
                     ok = best <= (int32_t)E;
                 }

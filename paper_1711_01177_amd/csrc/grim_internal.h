@@ -38,9 +38,13 @@ struct FilterArgs {
     int npl;                    // multiplicity planes reserved per read
 };
 
+// Zero words kept after the packed reference for the alignment check, whose
+// look-ahead fetches of reference words run up to three words past the end.
+constexpr uint64_t kRefPadWords = 4;
+
 // Arguments of the alignment-check kernel.
 struct VerifyArgs {
-    const uint32_t *ref;        // packed reference
+    const uint32_t *ref;        // packed reference, kRefPadWords zero words after its end
     uint64_t ref_words;
     uint64_t G, B, O, n_bins;
     const uint32_t *rw;
@@ -126,7 +130,8 @@ struct grim_index {
     int device;
     uint64_t B, O, G, n_bins, vector_bytes, bytes;
     void *d_vec;
-    uint32_t *d_ref;        // packed reference kept for alignment checks (or null)
+    uint32_t *d_ref;        // packed reference kept for alignment checks (or null),
+                            // followed by kRefPadWords zero words
     uint64_t ref_words;
     uint32_t *d_rows;       // token-major copy for the bin-window form (or null)
     uint64_t row_words;
