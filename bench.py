@@ -50,29 +50,6 @@ CONFIG_TEXT = {
 }
 
 
-def sample_check(w, counts_t, bits_t, n_samples, rng):
-    """Compare n_samples random pairs with the oracle, one pair at a time."""
-    import oracle
-    n = int(w["cand_off"][-1])
-    ks = np.sort(rng.choice(n, size=min(n, n_samples), replace=False))
-    import torch
-    idx = torch.from_numpy(ks.astype(np.int64)).to(counts_t.device)
-    gc = counts_t.index_select(0, idx).cpu().numpy()
-    gw = bits_t.index_select(0, torch.from_numpy((ks >> 5).astype(np.int64)).to(bits_t.device))
-    gb = ((gw.cpu().numpy().view(np.uint32) >> (ks & 31).astype(np.uint32)) & 1).astype(np.uint8)
-    reads = np.searchsorted(w["cand_off"], ks, side="right") - 1
-    bad = 0
-    for k, r, c, b in zip(ks, reads, gc, gb):
-        vec = oracle.build_bin(w["ref"], w["B"], w["O"], w["q"], int(w["cand_bin"][k]))
-        o = int(w["read_off"][r])
-        L = int(w["read_len"][r])
-        oc = oracle.count(vec, w["q"], w["codes"][o:o + L])
-        T = oracle.threshold(L, w["q"], oracle.max_edits(L, int(w["read_e"][r]), w["e_den"]))
-        if oc != c or int(oc >= T) != b:
-            bad += 1
-    return len(ks), bad
-
-
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -103,6 +80,51 @@ def cpu_baseline(w, target_pairs, n_threads, idx=None):
     dt = time.perf_counter() - t0
     return dict(pairs=n_pairs, reads=r1, seconds=dt, build_seconds=t_build,
                 pairs_per_s=n_pairs / dt), (c, p), idx
+
+
+def cpu_baseline_leg(w, counts, bits, n_threads, cpu_pairs=0):
+    """The oracle on the host cores (the CPU baseline, and the parity check of
+    the timed launch): the oracle's index is built (untimed), then the oracle
+    filter runs over every pair of the workload (or the first reads' pairs,
+    about cpu_pairs of them), n_threads threads taking chunks of about 4M pairs,
+    and every count and pass bit is compared with the GPU's (device tensors
+    counts and bits).  A single-thread run over about 2e7 pairs follows.
+    Returns (cpu_baseline dict, parity dict)."""
+    import oracle
+    n_pairs = int(w["cand_off"][-1])
+    n_reads = int(w["read_len"].size)
+    t0 = time.time()
+    oidx = oracle.build_index(w["ref"], w["B"], w["O"], w["q"], n_threads=n_threads)
+    t_build = time.time() - t0
+    r1 = n_reads
+    if cpu_pairs and cpu_pairs < n_pairs:
+        r1 = max(1, int(np.searchsorted(w["cand_off"], int(cpu_pairs), side="left")))
+    host_counts = counts[:n_pairs].cpu().numpy()
+    host_bits = bits[:(n_pairs + 31) // 32].cpu().numpy().view(np.uint32)
+    tc = time.perf_counter()
+    res = oracle.filter_compare(oidx, w["q"], w["codes"], w["read_off"], w["read_len"],
+                                w["read_e"], w["e_den"], w["cand_off"], w["cand_bin"],
+                                host_counts, host_bits, r_end=r1, n_threads=n_threads)
+    dt = time.perf_counter() - tc
+    del host_counts, host_bits
+    parity = dict(pairs=res["pairs"], reads=res["reads"], count_mismatches=res["count_mismatches"],
+                  bit_mismatches=res["bit_mismatches"], first_mismatches=res["first"],
+                  every_pair=res["pairs"] == n_pairs,
+                  note="every count and pass bit of the timed launch against the oracle")
+    c1, _, _ = cpu_baseline(w, int(2e7), 1, idx=oidx)
+    cpu = {"value": res["pairs"] / dt, "unit": "candidate locations/s", "cores": n_threads,
+           "kind": "oracle",
+           "sample": f"reads [0, {r1}) of the workload ({res['pairs']} pairs), filter phase "
+                     f"only (index build {t_build:.1f}s excluded), {dt:.1f}s on {n_threads} "
+                     f"threads taking chunks of about 4M pairs",
+           "single_thread_value": c1["pairs_per_s"],
+           "single_thread_sample": f"first {c1['reads']} reads ({c1['pairs']} pairs), "
+                                   f"{c1['seconds']:.1f}s on 1 thread",
+           "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
+    log(f"[bench] cpu oracle: {cpu['value']:.3e} pairs/s on {n_threads} threads ({dt:.1f}s); "
+        f"parity over {res['pairs']} pairs: {res['count_mismatches']} count and "
+        f"{res['bit_mismatches']} pass-bit mismatches (total {time.time() - t0:.1f}s)")
+    return cpu, parity
 
 
 def link_probe(torch, n_bytes=256 << 20, reps=5):
@@ -145,7 +167,7 @@ def link_probe(torch, n_bytes=256 << 20, reps=5):
 
 def serving_leg(g, idx, w, rng, loads=(0.25, 0.5, 0.75, 0.9), n_requests=10_000, pool=256,
                 max_reads=65536, inplace=True, tick_pairs=8 << 20, n_streams=3,
-                max_inflight=1024, fixed_rates=None, bits_only=False):
+                max_inflight=1024, fixed_rates=None, bits_only=False, expect=None):
     """Served latency.  A pool of `pool` requests of log-uniform size
     (1..max_reads reads) is cut from the workload.  First the server's capacity
     is measured closed-loop (a burst of requests submitted at once); then, for
@@ -159,9 +181,11 @@ def serving_leg(g, idx, w, rng, loads=(0.25, 0.5, 0.75, 0.9), n_requests=10_000,
     ticks (and at most max_inflight requests) are in flight at once.  fixed_rates (pairs per second)
     replaces the loads relative to capacity by absolute arrival rates, so that
     server configurations can be compared at the same offered traffic.
-    bits_only=True serves the pass bits alone (counts stay on the device)."""
+    bits_only=True serves the pass bits alone (counts stay on the device).
+    expect = (counts, pass-bit words) of the whole workload as host arrays:
+    with in-place submission every request's results are compared with them."""
     n_reads = w["read_len"].size
-    reqs = []
+    reqs, spans = [], []
     for _ in range(pool):
         size = int(min(n_reads, max(1, round(math.exp(rng.uniform(0, math.log(max_reads)))))))
         r0 = int(rng.integers(0, n_reads - size + 1))
@@ -172,6 +196,7 @@ def serving_leg(g, idx, w, rng, loads=(0.25, 0.5, 0.75, 0.9), n_requests=10_000,
         reqs.append(g.HostBatch(w["codes"][o0:o1], w["read_off"][r0:r1] - o0, w["read_len"][r0:r1],
                                 w["read_e"][r0:r1], w["e_den"], w["cand_off"][r0:r1 + 1] - c0,
                                 w["cand_bin"][c0:c1], max_len=250, pinned=inplace))
+        spans.append((r0, r1))
     mean_pairs = float(np.mean([hb.n_pairs for hb in reqs]))
     srv = g.Server(idx, hbm_budget_bytes=4 << 30, max_inflight=max_inflight, n_streams=n_streams,
                    max_tick_pairs=tick_pairs, max_len=256, pass_bits_only=bits_only)
@@ -197,6 +222,25 @@ def serving_leg(g, idx, w, rng, loads=(0.25, 0.5, 0.75, 0.9), n_requests=10_000,
         walls.append(time.perf_counter() - t0)
     capacity = sum(hb.n_pairs for hb in reqs) / float(np.mean(walls))
     cap_stats = srv.stats(reset=True)
+    checked = None
+    if expect is not None and inplace and not bits_only:
+        # every pool request's results, as the capacity bursts left them, against
+        # the timed batched launch's results for the same pairs (which the CPU
+        # baseline leg compares with the oracle pair by pair)
+        ec, eb = expect
+        checked = dict(requests=0, pairs=0, count_mismatches=0, bit_mismatches=0,
+                       largest_request_reads=max(r1 - r0 for r0, r1 in spans))
+        for (r0, r1), hb in zip(spans, reqs):
+            c0, c1 = int(w["cand_off"][r0]), int(w["cand_off"][r1])
+            n = c1 - c0
+            want_bits = np.unpackbits(eb.view(np.uint8)[c0 >> 3:(c1 + 7) >> 3],
+                                      bitorder="little")[c0 & 7:(c0 & 7) + n]
+            got_bits = np.unpackbits(hb.out_bits.view(np.uint8), bitorder="little")[:n]
+            checked["requests"] += 1
+            checked["pairs"] += n
+            checked["count_mismatches"] += int(np.count_nonzero(hb.out_counts[:n] != ec[c0:c1]))
+            checked["bit_mismatches"] += int(np.count_nonzero(got_bits != want_bits))
+        log(f"[bench] served results against the batched launch: {checked}")
     # bytes each request moves over the host link: inputs one way, counts and
     # pass bits (the tick's bits via the stage, then ORed in) back
     n_pairs_all = sum(hb.n_pairs for hb in reqs)
@@ -210,6 +254,7 @@ def serving_leg(g, idx, w, rng, loads=(0.25, 0.5, 0.75, 0.9), n_requests=10_000,
                capacity_burst_s=walls,
                capacity_pairs_per_s=capacity,
                capacity_ticks=cap_stats["ticks"],
+               results_checked=checked,
                link_bytes_per_pair=dict(up=up_bytes / n_pairs_all, down=down_bytes / n_pairs_all),
                points=[])
     points = [(rho, rho * capacity) for rho in loads] if fixed_rates is None else \
@@ -441,7 +486,9 @@ def main():
     ap.add_argument("--unroll", type=int, default=0)
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--wg", type=int, default=0)
-    ap.add_argument("--cpu-pairs", type=float, default=3.0e8)
+    ap.add_argument("--cpu-pairs", type=float, default=0,
+                    help="compare only the first reads' pairs (about this many) with the oracle "
+                         "(0: every pair)")
     ap.add_argument("--no-window", action="store_true", help="skip the bin-window leg")
     ap.add_argument("--no-seed", action="store_true",
                     help="skip the GPU seeding leg (mid recipe) of the default workload")
@@ -697,15 +744,20 @@ def main():
             f"reads pre-sorted by window: {window['presorted']['ms']:.3f} ms, "
             f"identical={window['presorted']['identical_per_read_bin']}")
 
-    check_n, check_bad = sample_check(w, counts, bits, 2000, rng)
-    log(f"[bench] sampled parity: {check_bad} mismatches in {check_n} pairs")
+    cpu, parity = None, None
+    if not args.no_cpu:
+        cpu, parity = cpu_baseline_leg(w, counts, bits, n_threads, args.cpu_pairs)
 
     serving = None
     if not args.no_serve:
         try:
             t0 = time.time()
             link = link_probe(torch)
-            serving = serving_leg(g, idx, w, rng, n_requests=args.serve_requests, inplace=True)
+            expect = (counts[:n_pairs].cpu().numpy(),
+                      bits[:(n_pairs + 31) // 32].cpu().numpy().view(np.uint32))
+            serving = serving_leg(g, idx, w, rng, n_requests=args.serve_requests, inplace=True,
+                                  expect=expect)
+            del expect
             # the link ceiling: both directions at once, the busier one decides
             bpp = serving["link_bytes_per_pair"]
             ceiling = link["both_each_gbs"] * 1e9 / max(bpp["up"], bpp["down"])
@@ -741,27 +793,6 @@ def main():
         except Exception as ex:  # report, keep the throughput line
             serving = dict(error=str(ex))
             log(f"[bench] serving leg failed: {ex}")
-
-    cpu = None
-    if not args.no_cpu:
-        t0 = time.time()
-        cb, (oc, op), oidx = cpu_baseline(w, int(args.cpu_pairs), n_threads)
-        same = bool(np.array_equal(oc, counts[:cb["pairs"]].cpu().numpy()))
-        del oc, op
-        # one thread, on a sample 1/16 the size
-        c1, _, _ = cpu_baseline(w, int(args.cpu_pairs / 16), 1, idx=oidx)
-        del oidx
-        cpu = {"value": cb["pairs_per_s"], "unit": "candidate locations/s", "cores": n_threads,
-               "kind": "oracle",
-               "sample": f"first {cb['reads']} reads of the workload ({cb['pairs']} pairs), "
-                         f"filter phase only, {cb['seconds']:.1f}s on {n_threads} threads; "
-                         f"GPU counts identical on the sample: {same}",
-               "single_thread_value": c1["pairs_per_s"],
-               "single_thread_sample": f"first {c1['reads']} reads ({c1['pairs']} pairs), "
-                                       f"{c1['seconds']:.1f}s on 1 thread",
-               "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
-        log(f"[bench] cpu oracle: {cb['pairs_per_s']:.3e} pairs/s on {n_threads} threads "
-            f"({cb['seconds']:.1f}s; total {time.time() - t0:.1f}s)")
 
     traffic = None
     try:
@@ -817,7 +848,7 @@ def main():
         "seed_location_checker": checker,
         "seeding": seeding,
         "bin_window": window,
-        "sampled_parity": {"pairs": check_n, "mismatches": check_bad},
+        "parity": parity,
         "serving": serving,
         "cpu_baseline": cpu,
     }

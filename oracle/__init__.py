@@ -152,6 +152,86 @@ class Oracle:
         _split(work, 0, n_reads, n_threads)
         return counts, passed, bad[0]
 
+    def filter_compare(self, index, q, read_codes, read_off, read_len, read_e_num, e_den,
+                       cand_off, cand_bin, counts, bits, r_begin=0, r_end=None, n_threads=1,
+                       chunk_pairs=1 << 22):
+        """Run the oracle filter over reads [r_begin, r_end) and compare every
+        pair with given results (host arrays over the whole batch: int32
+        counts[n_pairs], uint32 pass-bit words).
+
+        The reads are cut at read boundaries into chunks of about chunk_pairs
+        pairs; n_threads threads take chunks from a shared queue, each running
+        the plain oracle_filter on its chunk alone, so that Zipf-skewed
+        candidate counts still spread evenly.  Only the oracle's own results
+        are compared with; nothing of the given results enters its arithmetic.
+        Returns dict(pairs, reads, count_mismatches, bit_mismatches,
+        out_of_range, first) with up to 8 mismatching pair indices in first."""
+        index = _c(index, np.uint8)
+        n_bins = index.shape[0] if index.ndim == 2 else index.size // self.vector_bytes(q)
+        read_codes = _c(read_codes, np.uint8)
+        read_off = _c(read_off, np.uint64)
+        read_len = _c(read_len, np.uint32)
+        read_e_num = _c(read_e_num, np.uint32)
+        cand_off = _c(cand_off, np.uint64)
+        cand_bin = _c(cand_bin, np.uint32)
+        counts = np.ascontiguousarray(counts).view(np.int32)
+        bytes_ = np.ascontiguousarray(bits).view(np.uint32).view(np.uint8)
+        n_reads = read_len.size
+        r_end = n_reads if r_end is None else int(r_end)
+        r_begin = int(r_begin)
+        # chunk boundaries: read indices where the pair offset crosses a multiple
+        # of chunk_pairs (every chunk holds at least one read)
+        marks = np.arange(int(cand_off[r_begin]), int(cand_off[r_end]), int(chunk_pairs),
+                          dtype=np.uint64)
+        cuts = np.searchsorted(cand_off[r_begin:r_end + 1], marks, side="right") - 1 + r_begin
+        cuts = np.unique(np.concatenate([cuts, [r_begin, r_end]]).astype(np.int64))
+        cuts = cuts[(cuts >= r_begin) & (cuts <= r_end)]
+        chunks = list(zip(cuts[:-1].tolist(), cuts[1:].tolist()))
+        lib = self.lib
+        lock = threading.Lock()
+        res = dict(pairs=0, reads=r_end - r_begin, count_mismatches=0, bit_mismatches=0,
+                   out_of_range=0, first=[])
+        nxt = [0]
+
+        def work():
+            while True:
+                with lock:
+                    if nxt[0] >= len(chunks):
+                        return
+                    a, b = chunks[nxt[0]]
+                    nxt[0] += 1
+                pa, pb = int(cand_off[a]), int(cand_off[b])
+                n = pb - pa
+                sub_off = cand_off[a:b + 1] - np.uint64(pa)
+                oc = np.empty(max(1, n), dtype=np.int32)
+                op = np.empty(max(1, n), dtype=np.uint8)
+                bad = lib.oracle_filter(_ptr(index, _u8p), n_bins, q, _ptr(read_codes, _u8p),
+                                        _ptr(read_off[a:b], _u64p), _ptr(read_len[a:b], _u32p),
+                                        _ptr(read_e_num[a:b], _u32p), e_den, 0, b - a,
+                                        _ptr(sub_off, _u64p),
+                                        _ptr(cand_bin[pa:pb] if n else cand_bin, _u32p),
+                                        _ptr(oc, _i32p), _ptr(op, _u8p))
+                gc = counts[pa:pb]
+                cm = np.nonzero(gc != oc[:n])[0]
+                s = pa & 7
+                gb = np.unpackbits(bytes_[pa >> 3:(pb + 7) >> 3], bitorder="little")[s:s + n]
+                bm = np.nonzero(gb != op[:n])[0]
+                with lock:
+                    res["pairs"] += n
+                    res["out_of_range"] += int(bad)
+                    res["count_mismatches"] += int(cm.size)
+                    res["bit_mismatches"] += int(bm.size)
+                    for k in np.concatenate([cm, bm])[:8]:
+                        if len(res["first"]) < 8:
+                            res["first"].append(pa + int(k))
+
+        ths = [threading.Thread(target=work) for _ in range(max(1, int(n_threads)))]
+        for t in ths:
+            t.start()
+        for t in ths:
+            t.join()
+        return res
+
     def pack_bitmask(self, passed):
         passed = _c(passed, np.uint8)
         words = np.zeros((passed.size + 31) // 32, dtype=np.uint32)
@@ -242,7 +322,8 @@ def _fwd(name):
 
 
 for _n in ("num_bins", "vector_bytes", "token", "max_edits", "num_tokens", "threshold",
-           "build_bin", "build_index", "count", "filter_batch", "pack_bitmask", "survivors",
+           "build_bin", "build_index", "count", "filter_batch", "filter_compare", "pack_bitmask",
+           "survivors",
            "edit_distance_in_bin", "verify", "seed_candidates"):
     globals()[_n] = _fwd(_n)
 

@@ -9,7 +9,8 @@ import numpy as np
 import pytest
 
 import grim_synth as gs
-from tests.gpu_helpers import lib, oracle_run
+import oracle
+from tests.gpu_helpers import lib
 
 pytestmark = pytest.mark.gpu
 
@@ -24,7 +25,17 @@ def setup():
     g = lib()
     w = gs.make_workload("serve", scale=0.003)  # 9.3 Mbp, 12k reads, Zipf candidates
     idx = g.grim_build_bins(w["ref"], w["q"], w["B"], w["O"])
+    w["oidx"] = oracle.build_index(w["ref"], w["B"], w["O"], w["q"], n_threads=gs.default_threads())
     return g, w, idx
+
+
+def oracle_check(w, sub, c, b):
+    """A request's counts and pass bits against the oracle, pair by pair."""
+    res = oracle.filter_compare(w["oidx"], w["q"], sub["codes"], sub["read_off"], sub["read_len"],
+                                sub["read_e"], sub["e_den"], sub["cand_off"], sub["cand_bin"],
+                                c, b, n_threads=gs.default_threads())
+    assert res["pairs"] == int(sub["cand_off"][-1])
+    return res["count_mismatches"] == 0 and res["bit_mismatches"] == 0
 
 
 def cut(g, w, r0, r1, max_len=256):
@@ -69,10 +80,9 @@ def test_alone_vs_mix(setup):
     reqs = make_requests(g, w, 80, 11)
     say("requests", len(reqs), "pairs", sum(hb.n_pairs for _, hb in reqs))
     solo = [alone(g, idx, sub) for sub, _ in reqs]
-    # a few solo results against the oracle too
-    for (sub, _), (rc, c, b) in list(zip(reqs, solo))[:5]:
-        oc, ob, bad, _ = oracle_run(sub)
-        assert rc == 0 and np.array_equal(c, oc) and np.array_equal(b, ob)
+    # every solo result against the oracle
+    for i, ((sub, _), (rc, c, b)) in enumerate(zip(reqs, solo)):
+        assert rc == 0 and oracle_check(w, sub, c, b), f"request {i} differs from the oracle"
     srv = g.Server(idx, hbm_budget_bytes=256 << 20, max_inflight=16, n_streams=3,
                    max_tick_pairs=1 << 20, max_len=256)
     tickets = [None] * len(reqs)
