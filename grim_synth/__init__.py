@@ -22,6 +22,7 @@ bit-identical for any thread count).
 ``scale`` shrinks genome and read counts proportionally for tests.
 """
 import ctypes
+import hashlib
 import os
 import subprocess
 import threading
@@ -31,6 +32,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "synth.c")
 _LIB = os.path.join(_HERE, "libgrimsynth.so")
+_DEFAULT_LIB = _LIB
 _lib = None
 _lock = threading.Lock()
 
@@ -41,12 +43,45 @@ _u32p = ctypes.POINTER(ctypes.c_uint32)
 _u64p = ctypes.POINTER(ctypes.c_uint64)
 
 
-def build():
-    """Compile synth.c into libgrimsynth.so (always recompiles)."""
-    tmp = _LIB + ".tmp"
-    subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-Wall", "-shared", "-fPIC", _SRC,
-                           "-o", tmp, "-lpthread", "-lm"])
-    os.replace(tmp, _LIB)
+_CFLAGS = ["-O2", "-std=gnu11", "-Wall", "-shared", "-fPIC"]
+
+
+def _stamp(src, flags):
+    """Hash of the source text and the compile flags a build used."""
+    h = hashlib.sha1()
+    with open(src, "rb") as f:
+        h.update(f.read())
+    h.update(" ".join(flags).encode())
+    return h.hexdigest()
+
+
+def build(out=None, extra_flags=()):
+    """Compile synth.c into libgrimsynth.so (always recompiles).  A stamp file
+    next to the library records the hash of the source and flags, so that a
+    library older than its source is never loaded by default."""
+    out = out or _LIB
+    flags = _CFLAGS + list(extra_flags)
+    tmp = out + ".tmp"
+    subprocess.check_call(["gcc", *flags, _SRC, "-o", tmp, "-lpthread", "-lm"])
+    os.replace(tmp, out)
+    with open(out + ".stamp", "w") as f:
+        f.write(_stamp(_SRC, flags))
+
+
+def _current():
+    try:
+        with open(_LIB + ".stamp") as f:
+            return os.path.exists(_LIB) and f.read().strip() == _stamp(_SRC, _CFLAGS)
+    except OSError:
+        return False
+
+
+def use_library(path):
+    """Bind the generators to another build of synth.c (e.g. a sanitizer build)."""
+    global _LIB, _lib
+    with _lock:
+        _LIB = path
+        _lib = None
 
 
 def _load():
@@ -54,7 +89,7 @@ def _load():
     with _lock:
         if _lib is not None:
             return _lib
-        if not os.path.exists(_LIB):
+        if not os.path.exists(_LIB) or (_LIB == _DEFAULT_LIB and not _current()):
             build()
         lib = ctypes.CDLL(_LIB)
         u64, u32, dbl, i32 = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_double, ctypes.c_int

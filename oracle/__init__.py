@@ -9,6 +9,7 @@ benchmark may import this package; the product library never does.
 All sequences are numpy ``uint8`` arrays of base codes A=0 C=1 G=2 T=3.
 """
 import ctypes
+import hashlib
 import os
 import subprocess
 import threading
@@ -27,12 +28,36 @@ _u64p = ctypes.POINTER(ctypes.c_uint64)
 _i32p = ctypes.POINTER(ctypes.c_int32)
 
 
-def build(src=_SRC, out=_LIB):
-    """Compile oracle.c into a shared library with gcc (always recompiles)."""
+_CFLAGS = ["-O2", "-std=c11", "-Wall", "-Wextra", "-shared", "-fPIC"]
+
+
+def _stamp(src, flags):
+    """Hash of the source text and the compile flags a build used."""
+    h = hashlib.sha1()
+    with open(src, "rb") as f:
+        h.update(f.read())
+    h.update(" ".join(flags).encode())
+    return h.hexdigest()
+
+
+def build(src=_SRC, out=_LIB, extra_flags=()):
+    """Compile oracle.c into a shared library with gcc (always recompiles).
+    A stamp file next to the library records the hash of the source and flags,
+    so that a library older than its source is never loaded by default."""
+    flags = _CFLAGS + list(extra_flags)
     tmp = out + ".tmp"
-    subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-shared", "-fPIC",
-                           src, "-o", tmp])
+    subprocess.check_call(["gcc", *flags, src, "-o", tmp])
     os.replace(tmp, out)
+    with open(out + ".stamp", "w") as f:
+        f.write(_stamp(src, flags))
+
+
+def _current(src=_SRC, out=_LIB):
+    try:
+        with open(out + ".stamp") as f:
+            return os.path.exists(out) and f.read().strip() == _stamp(src, _CFLAGS)
+    except OSError:
+        return False
 
 
 class Oracle:
@@ -299,7 +324,7 @@ def _default():
     global _lib
     with _lock:
         if _lib is None:
-            if not os.path.exists(_LIB):
+            if not _current():
                 build()
             _lib = Oracle(_LIB)
         return _lib

@@ -190,7 +190,10 @@ __global__ __launch_bounds__(256) void filter_batched_kernel(FilterArgs a)
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int npl = a.npl;
     const uint32_t mask_words = a.tile_pairs >> 5;
-    uint32_t *planes = lds + (size_t)wv * (npl * VW + mask_words);
+    // each wave's region: its planes, then the tile's pass-bit words rounded up
+    // to whole 16-byte units, so that every region (and plane) starts 16-byte
+    // aligned for the uint4 plane reads
+    uint32_t *planes = lds + (size_t)wv * (npl * VW + ((mask_words + 3u) & ~3u));
     uint32_t *tmask = planes + npl * VW;
     const int g = lane / G, lg = lane % G;
 
