@@ -376,15 +376,34 @@ def seeding_leg(g, torch, stream):
     return out
 
 
-def window_leg(g, idx, w, torch, stream, rng, window_bins=4096, n_reads=200_000):
+def window_lo(tb, n_bins, window_bins=4096, align=1024):
+    """First bin of each read's window: window_bins bins around its true bin
+    tb, starting on a multiple of `align` bins (1: no alignment), inside the
+    index.  A window that would run past the last bin starts at
+    n_bins - window_bins instead (unaligned); the true bin is always inside."""
+    tb = np.asarray(tb, dtype=np.int64)
+    lo = np.maximum(tb - window_bins // 2, 0)
+    lo = (lo // align) * align
+    last = max(0, n_bins - window_bins)
+    lo = np.where(lo > last, last, lo)
+    assert np.all((tb >= lo) & (tb < lo + window_bins)), "a true bin outside its window"
+    return lo.astype(np.uint32)
+
+
+def window_leg(g, idx, w, torch, stream, rng, window_bins=4096, n_reads=200_000, align=1024):
     """The bin-window form: each of n_reads reads against the window_bins
-    consecutive bins around its true bin, from the token-major index copy.
-    Compared with the batched random-gather kernel on the same explicit pairs
-    (identical outputs checked) and timed with HIP events."""
+    consecutive bins around its true bin, from the token-major index copy.  The
+    mapper's windows start on multiples of `align` bins (a 4096-bin window then
+    covers exactly four 128-byte lines of every token row); the same windows
+    unaligned are timed as well.  Compared with the batched random-gather
+    kernel on the same explicit pairs (identical outputs checked) and timed
+    with HIP events."""
     n_reads = min(n_reads, w["read_len"].size)
     n_bins = idx.n_bins
     tb = (w["read_z"][:n_reads] // w["B"]).astype(np.int64)
-    lo = np.clip(tb - window_bins // 2, 0, n_bins - window_bins).astype(np.uint32)
+    lo = window_lo(tb, n_bins, window_bins, align)
+    lo_unaligned = window_lo(tb, n_bins, window_bins, 1)
+    assert np.all((tb >= lo) & (tb < lo.astype(np.int64) + window_bins))
     off = np.arange(n_reads + 1, dtype=np.uint64) * window_bins
     o_end = int(w["read_off"][n_reads - 1]) + int(w["read_len"][n_reads - 1])
     t0 = time.time()
@@ -407,6 +426,19 @@ def window_leg(g, idx, w, torch, stream, rng, window_bins=4096, n_reads=200_000)
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / 5
+    # the same reads with windows that start anywhere (row segments then span
+    # five 128-byte lines)
+    wlu = torch.from_numpy(lo_unaligned.view(np.int32)).cuda()
+    cu, bu = g.alloc_outputs(n)
+    g.grim_filter_windows(idx, wb, wlu, cu, bu, ws)
+    rc_unaligned, _ = g.grim_filter_status(ws)
+    e0.record(stream)
+    for _ in range(5):
+        g.grim_filter_windows(idx, wb, wlu, cu, bu, ws)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_unaligned = e0.elapsed_time(e1) / 5
+    del cu, bu, wlu
     # the same reads submitted sorted by window start (a caller's choice, made on
     # the host outside the timing): concurrent workgroups then share row
     # segments through L2; outputs equal the index-order ones per (read, bin)
@@ -452,11 +484,15 @@ def window_leg(g, idx, w, torch, stream, rng, window_bins=4096, n_reads=200_000)
     same = bool(torch.equal(c1[:n], c2[:n]) and torch.equal(b1[:(n + 31) // 32], b2[:(n + 31) // 32]))
     ntok = float(np.mean(np.maximum(w["read_len"][:n_reads].astype(np.int64) - w["q"] + 1, 0)))
     row_bytes = ntok * window_bins / 8 + window_bins * (4 + 1 / 8)
-    out = dict(window_bins=window_bins, reads=n_reads, pairs=n, ms=ms, pairs_per_s=n / (ms * 1e-3),
+    out = dict(window_bins=window_bins, window_align_bins=align, reads=n_reads, pairs=n, ms=ms,
+               pairs_per_s=n / (ms * 1e-3),
                status=rc, identical=same, batched_same_pairs_ms=ms_batched,
                speedup_vs_batched_same_pairs=ms_batched / ms, transpose_s=t_transpose,
                algorithmic_bytes_per_window=row_bytes,
                algorithmic_gbs=n_reads * row_bytes / (ms * 1e-3) / 1e9,
+               unaligned=dict(ms=ms_unaligned, pairs_per_s=n / (ms_unaligned * 1e-3),
+                              status=rc_unaligned,
+                              algorithmic_gbs=n_reads * row_bytes / (ms_unaligned * 1e-3) / 1e9),
                presorted=dict(note="the same reads submitted sorted by window start "
                                    "(host argsort outside the timing)",
                               ms=ms_sorted, pairs_per_s=n / (ms_sorted * 1e-3),

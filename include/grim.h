@@ -140,6 +140,8 @@ void grim_index_free(grim_index_t *idx);
  * Full Read Mapper": the mapper sends each read with the seed locations its
  * hash table returned).  All pointers are device pointers for grim_filter_*,
  * host pointers for grim_serve_submit. */
+#define GRIM_MAX_READ_LEN 8192u   /* longest read any entry point accepts */
+
 typedef struct grim_batch {
     const uint32_t *reads_2bit;   /* packed bases of all reads                     */
     uint64_t n_read_words;        /* words readable at reads_2bit                  */
@@ -147,7 +149,7 @@ typedef struct grim_batch {
     const uint32_t *read_len;     /* [n_reads] L                                   */
     const uint32_t *read_e;       /* [n_reads] error tolerance numerator e_num     */
     uint32_t e_den;               /* tolerance denominator (e.g. 10000), > 0       */
-    uint32_t max_len;             /* upper bound on every L, 1..8192               */
+    uint32_t max_len;             /* upper bound on every L, 1..GRIM_MAX_READ_LEN  */
     const uint64_t *cand_off;     /* [n_reads + 1] CSR offsets, cand_off[0] = 0,   */
                                   /* non-decreasing, cand_off[n_reads] = n_pairs   */
     const uint32_t *cand_bin;     /* [n_pairs] candidate bin ids (bin_num(z))      */

@@ -10,7 +10,7 @@
 namespace grim {
 
 constexpr int kWave = 64;
-constexpr uint32_t kMaxLen = 8192;       // longest read the kernels accept
+constexpr uint32_t kMaxLen = GRIM_MAX_READ_LEN;  // longest read the kernels accept
 constexpr uint64_t kWsHeader = 256;      // status word + tile counter, padded
 
 // Arguments of both filter kernels (passed by value).

@@ -24,8 +24,13 @@
 // Fusing and splitting only concatenate, cut and re-base offsets, and every
 // pair is computed by the same kernel from the same read and bin, so each
 // request's counts and pass bits are identical to filtering it alone.
-#include <hip/hip_runtime.h>
-
+//
+// The scheduler makes no HIP call itself: device memory, streams, copies, the
+// filter launch and completion notices go through grim_serve::backend()
+// (grim_serve_backend.h).  A tick's completion is signalled by a host function
+// queued on its stream after its last copy; it marks the slot finished and
+// rings the scheduler's doorbell, which is the only thing the scheduler waits
+// on (submissions and shutdown ring it too), so nothing polls.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -40,7 +45,10 @@
 #include <thread>
 #include <vector>
 
-#include "grim_internal.h"
+#include "grim.h"
+#include "grim_serve_backend.h"
+
+using grim_serve::backend;
 
 namespace {
 
@@ -255,11 +263,12 @@ struct Part {
 };
 
 struct Slot {
-    hipStream_t stream = nullptr;
-    hipEvent_t done = nullptr;
+    grim_server *srv = nullptr;
+    void *stream = nullptr;
     uint8_t *stage = nullptr;      // pinned staging buffer, mirrors the tick layout
     uint64_t stage_bytes = 0;
     bool busy = false;
+    std::atomic<bool> finished{false};  // set by the tick's completion notice
     std::vector<Part> parts;
     Layout lay;
     uint64_t dev_off = 0;
@@ -278,16 +287,23 @@ struct grim_server {
     uint64_t arena_bytes = 0;
     std::unique_ptr<Pool> arena_pool;
     std::mutex arena_mu;
-    std::vector<Slot> slots;
+    std::vector<std::unique_ptr<Slot>> slots;
+    uint64_t stage_bytes = 0;          // each slot's staging buffer: the largest tick layout
 
     std::mutex mu;
-    std::condition_variable cv_work, cv_done;
+    std::condition_variable cv_done;
     std::deque<std::shared_ptr<Request>> queue;
     std::map<uint64_t, std::shared_ptr<Request>> all;
     uint64_t next_ticket = 1, next_tick = 1;
     uint64_t inflight_reqs = 0;
     bool stop = false;
     std::thread thr;
+
+    // doorbell: rung by submissions, completion notices and shutdown; the
+    // scheduler sleeps until it changes (bell_mu is never held while taking mu)
+    std::mutex bell_mu;
+    std::condition_variable bell_cv;
+    uint64_t bell = 0;
 
     // statistics
     uint64_t submitted = 0, completed = 0, cancelled = 0, failed = 0, ticks = 0, pairs_done = 0;
@@ -298,6 +314,7 @@ struct grim_server {
     Clock::time_point busy_since;
 
     void run();
+    void ring();
     bool launch_tick(std::unique_lock<std::mutex> &lk);
     void retire(Slot &s);
     void part_closed(Request &r, Clock::time_point now);
@@ -305,13 +322,33 @@ struct grim_server {
     void free_block(Request &r);
 };
 
+void grim_server::ring()
+{
+    {
+        std::lock_guard<std::mutex> bl(bell_mu);
+        ++bell;
+    }
+    bell_cv.notify_one();
+}
+
+namespace {
+
+// Completion notice of a tick (runs on a backend thread once the tick's last
+// copy has completed): mark the slot and wake the scheduler.
+void on_tick_done(void *arg)
+{
+    Slot *slot = static_cast<Slot *>(arg);
+    slot->finished.store(true, std::memory_order_release);
+    slot->srv->ring();
+}
+
+}  // namespace
+
 namespace {
 
 uint64_t ws_need(const grim_index_t *idx, uint64_t n_pairs)
 {
-    uint64_t b = 0;
-    grim_workspace_size(idx, n_pairs, nullptr, &b);
-    return b;
+    return backend().workspace_bytes(idx, n_pairs);
 }
 
 }  // namespace
@@ -404,9 +441,9 @@ void grim_server::retire(Slot &s)
         for (const Part &pt : s.parts)
             n = std::max(n, pt.fused_base + (pt.pb - pt.pa));
         const uint8_t *dout = pool_base + s.dev_off + s.lay.out_base;
-        if (hipMemcpyAsync(s.stage + s.lay.out_base + s.lay.counts, dout + s.lay.counts, n * 4,
-                           hipMemcpyDeviceToHost, s.stream) != hipSuccess ||
-            hipStreamSynchronize(s.stream) != hipSuccess) {
+        if (backend().copy_d2h(s.stage + s.lay.out_base + s.lay.counts, dout + s.lay.counts,
+                               n * 4, s.stream) != GRIM_OK ||
+            backend().stream_sync(s.stream) != GRIM_OK) {
             for (Part &pt : s.parts)  // cannot tell which: fail them all
                 pt.r->status = GRIM_E_HIP;
         }
@@ -433,6 +470,7 @@ void grim_server::retire(Slot &s)
     pool->release(s.dev_off, s.lay.total);
     s.parts.clear();
     s.busy = false;
+    s.finished.store(false, std::memory_order_relaxed);
     if (--running_ticks == 0)
         busy_s += std::chrono::duration<double>(now - busy_since).count();
     cv_done.notify_all();
@@ -445,16 +483,15 @@ namespace {
 // block, consecutive small slices packed in the stage and sent as one run.
 struct SectionCopier {
     uint8_t *dev, *stage;
-    hipStream_t s;
+    void *s;
     uint64_t run_lo = 0, run_hi = 0;
     bool run = false;
-    hipError_t err = hipSuccess;
+    int err = GRIM_OK;
 
     void flush()
     {
-        if (run && run_hi > run_lo && err == hipSuccess)
-            err = hipMemcpyAsync(dev + run_lo, stage + run_lo, run_hi - run_lo,
-                                 hipMemcpyHostToDevice, s);
+        if (run && run_hi > run_lo && err == GRIM_OK)
+            err = backend().copy_h2d(dev + run_lo, stage + run_lo, run_hi - run_lo, s);
         run = false;
     }
     void add(uint64_t off, const void *src, uint64_t bytes)
@@ -463,8 +500,8 @@ struct SectionCopier {
             return;
         if (bytes >= kDirectBytes) {
             flush();
-            if (err == hipSuccess)
-                err = hipMemcpyAsync(dev + off, src, bytes, hipMemcpyHostToDevice, s);
+            if (err == GRIM_OK)
+                err = backend().copy_h2d(dev + off, src, bytes, s);
             return;
         }
         std::memcpy(stage + off, src, bytes);
@@ -487,23 +524,24 @@ bool grim_server::launch_tick(std::unique_lock<std::mutex> &lk)
 {
     Slot *slot = nullptr;
     for (auto &s : slots)
-        if (!s.busy) {
-            slot = &s;
+        if (!s->busy) {
+            slot = s.get();
             break;
         }
     if (!slot || queue.empty())
         return false;
     // admission: requests in arrival order with the e_den of the first one
-    // taken, within max_inflight, the tick's pair limit and the free budget; the
-    // request that does not fit the pair limit whole contributes the reads that
-    // do (at least one read when the tick would be empty) and stays queued.  A
-    // request already running in n_streams - 1 parts is passed over, so that
-    // one stream always remains for the requests behind it.
+    // taken, within max_inflight, the tick's pair limit, the free budget and
+    // the staging buffer; the request that does not fit whole contributes the
+    // reads that do (at least one read when the tick would be empty and its
+    // pairs exceed the pair limit) and stays queued.  A request already running
+    // in n_streams - 1 parts is passed over, so that one stream always remains
+    // for the requests behind it.
     std::vector<Part> take;
     uint64_t words = 0, reads = 0, pairs = 0, new_reqs = 0;
     uint32_t e_den = 0;
     const uint32_t max_parts = slots.size() > 1 ? (uint32_t)slots.size() - 1 : 1u;
-    const uint64_t free_bytes = cfg.hbm_budget_bytes - pool->used();
+    const uint64_t cap = std::min<uint64_t>(cfg.hbm_budget_bytes - pool->used(), stage_bytes);
     for (auto it = queue.begin(); it != queue.end();) {
         std::shared_ptr<Request> rp = *it;
         Request &r = *rp;
@@ -516,49 +554,57 @@ bool grim_server::launch_tick(std::unique_lock<std::mutex> &lk)
             e_den = r.e_den;
         if (r.e_den != e_den || (first && inflight_reqs + new_reqs >= cfg.max_inflight))
             break;
+        auto fits = [&](uint64_t nw, uint64_t nr, uint64_t np) {
+            return plan(words + nw + 1, reads + nr, pairs + np, ws_need(idx, pairs + np)).total <=
+                   cap;
+        };
         const uint64_t room = cfg.max_tick_pairs > pairs ? cfg.max_tick_pairs - pairs : 0;
         const uint64_t *co = r.cand_off();
         Part pt;
         pt.r = rp;
         pt.ra = r.next_read;
         if (r.n_reads == 0) {
+            if (!fits(0, 0, 0))
+                break;
             pt.rb = 0;
-        } else {
-            // last read end rb with co[rb] - co[ra] <= room
-            const uint64_t lim = co[pt.ra] + room;
-            const uint64_t *e = std::upper_bound(co + pt.ra + 1, co + r.n_reads + 1, lim);
-            pt.rb = (uint64_t)(e - co) - 1;
-            if (pt.rb <= pt.ra) {
-                if (!take.empty())
-                    break;
-                pt.rb = pt.ra + 1;
-            }
-        }
-        pt.pa = r.n_reads ? co[pt.ra] : 0;
-        pt.pb = r.n_reads ? co[pt.rb] : 0;
-        if (pt.ra == 0 && pt.rb == r.n_reads) {
+        } else if (pt.ra == 0 && co[r.n_reads] <= room && fits(r.n_words, r.n_reads, co[r.n_reads])) {
+            pt.rb = r.n_reads;  // the whole request
             pt.wlo = 0;
             pt.nw = r.n_words;
         } else {
-            uint64_t lo = ~0ull, hi = 0;
+            // reads [ra, rb) within the pair room (one read at least when the
+            // tick is empty), cut further where the layout stops fitting
+            const uint64_t lim = co[pt.ra] + room;
+            uint64_t rb =
+                (uint64_t)(std::upper_bound(co + pt.ra + 1, co + r.n_reads + 1, lim) - co) - 1;
+            if (rb <= pt.ra) {
+                if (!take.empty())
+                    break;
+                rb = pt.ra + 1;
+            }
             const uint64_t *ro = r.read_off();
             const uint32_t *rl = r.read_len();
-            for (uint64_t i = pt.ra; i < pt.rb; ++i) {
-                lo = std::min<uint64_t>(lo, ro[i] >> 4);
-                hi = std::max<uint64_t>(hi, (ro[i] + rl[i] + 15) >> 4);
+            uint64_t lo = ~0ull, hi = 0, end = pt.ra;
+            for (uint64_t i = pt.ra; i < rb; ++i) {
+                const uint64_t nlo = std::min<uint64_t>(lo, ro[i] >> 4);
+                const uint64_t nhi = std::max<uint64_t>(hi, (ro[i] + rl[i] + 15) >> 4);
+                if (!fits(nhi - nlo, i + 1 - pt.ra, co[i + 1] - co[pt.ra]))
+                    break;
+                lo = nlo;
+                hi = nhi;
+                end = i + 1;
             }
-            hi = std::min<uint64_t>(std::max(hi, lo), r.n_words);
+            if (end == pt.ra)  // not one more read fits: wait for memory
+                break;
+            pt.rb = end;
             pt.wlo = lo;
             pt.nw = hi - lo;
         }
-        const uint64_t np = pt.pb - pt.pa, nr = pt.rb - pt.ra;
-        const uint64_t total =
-            plan(words + pt.nw + 1, reads + nr, pairs + np, ws_need(idx, pairs + np)).total;
-        if (total > free_bytes)
-            break;
+        pt.pa = r.n_reads ? co[pt.ra] : 0;
+        pt.pb = r.n_reads ? co[pt.rb] : 0;
         words += pt.nw;
-        reads += nr;
-        pairs += np;
+        reads += pt.rb - pt.ra;
+        pairs += pt.pb - pt.pa;
         if (first)
             ++new_reqs;
         take.push_back(pt);
@@ -596,6 +642,7 @@ bool grim_server::launch_tick(std::unique_lock<std::mutex> &lk)
         ++r.parts_open;
     }
     slot->busy = true;
+    slot->finished.store(false, std::memory_order_relaxed);
     slot->lay = lay;
     slot->dev_off = off;
     slot->tick = tick;
@@ -605,179 +652,185 @@ bool grim_server::launch_tick(std::unique_lock<std::mutex> &lk)
     reqs_in_ticks += take.size();
 
     lk.unlock();
+    const grim_serve::Backend &be = backend();
     int rc = GRIM_OK;
-    if (slot->stage_bytes < lay.total) {
-        if (slot->stage)
-            (void)hipHostFree(slot->stage);
-        const uint64_t nb = std::max<uint64_t>(lay.total, slot->stage_bytes * 2);
-        if (hipHostMalloc(reinterpret_cast<void **>(&slot->stage), nb, hipHostMallocDefault) !=
-            hipSuccess) {
-            slot->stage = nullptr;
-            slot->stage_bytes = 0;
-            rc = GRIM_E_NOMEM;
-        } else {
-            slot->stage_bytes = nb;
+    uint8_t *h = slot->stage;
+    uint8_t *d = pool_base + off;
+    void *st = slot->stream;
+    SectionCopier cw{d, h, st}, cl{d, h, st}, ce{d, h, st}, cb{d, h, st};
+    uint64_t wbase = 0, rbase = 0, pbase = 0;
+    uint64_t *ro = reinterpret_cast<uint64_t *>(h + lay.read_off);
+    uint64_t *coff = reinterpret_cast<uint64_t *>(h + lay.cand_off);
+    for (auto &pt : take) {
+        Request &r = *pt.r;
+        const uint64_t nr = pt.rb - pt.ra, np = pt.pb - pt.pa;
+        cw.add(lay.words + wbase * 4, r.words() + pt.wlo, pt.nw * 4);
+        const uint64_t *sro = r.read_off(), *sco = r.cand_off();
+        const uint64_t shift = wbase * 16, base0 = pt.wlo * 16;
+        for (uint64_t i = 0; i < nr; ++i) {
+            ro[rbase + i] = sro[pt.ra + i] - base0 + shift;
+            coff[rbase + i] = sco[pt.ra + i] - pt.pa + pbase;
         }
+        if (nr) {
+            cl.add(lay.read_len + rbase * 4, r.read_len() + pt.ra, nr * 4);
+            ce.add(lay.read_e + rbase * 4, r.read_e() + pt.ra, nr * 4);
+        }
+        if (np)
+            cb.add(lay.cand_bin + pbase * 4, r.cand_bin() + pt.pa, np * 4);
+        pt.fused_base = pbase;
+        wbase += pt.nw;
+        rbase += nr;
+        pbase += np;
     }
+    coff[rbase] = pbase;
+    const uint32_t zero = 0;
+    cw.add(lay.words + wbase * 4, &zero, 4);  // trailing word read by tokens at the end
+    cw.flush();
+    cl.flush();
+    ce.flush();
+    cb.flush();
+    int e = cw.err != GRIM_OK ? cw.err : cl.err != GRIM_OK ? cl.err : ce.err != GRIM_OK ? ce.err
+          : cb.err;
+    if (e == GRIM_OK)
+        e = be.copy_h2d(d + lay.read_off, h + lay.read_off, rbase * 8, st);
+    if (e == GRIM_OK)
+        e = be.copy_h2d(d + lay.cand_off, h + lay.cand_off, (rbase + 1) * 8, st);
+    if (e != GRIM_OK)
+        rc = GRIM_E_HIP;
+    grim_batch_t b;
+    b.reads_2bit = reinterpret_cast<const uint32_t *>(d + lay.words);
+    b.n_read_words = wbase + 1;
+    b.read_off = reinterpret_cast<const uint64_t *>(d + lay.read_off);
+    b.read_len = reinterpret_cast<const uint32_t *>(d + lay.read_len);
+    b.read_e = reinterpret_cast<const uint32_t *>(d + lay.read_e);
+    b.e_den = e_den;
+    b.max_len = cfg.max_len;
+    b.cand_off = reinterpret_cast<const uint64_t *>(d + lay.cand_off);
+    b.cand_bin = reinterpret_cast<const uint32_t *>(d + lay.cand_bin);
+    b.n_reads = rbase;
+    b.n_pairs = pbase;
+    uint8_t *dout = d + lay.out_base;
+    uint8_t *hout = h + lay.out_base;
+    int32_t *dcounts = reinterpret_cast<int32_t *>(dout + lay.counts);
+    uint32_t *dbits = reinterpret_cast<uint32_t *>(dout + lay.bits);
+    if (rc == GRIM_OK)
+        rc = be.filter(idx, &b, dcounts, dbits, d + lay.ws, lay.ws_bytes, st);
+    // results: large count slices straight into the request's result area, the
+    // rest (small slices, all pass bits, the status word) via the stage; no
+    // counts at all when only the pass bits are results; then the completion
+    // notice
     if (rc == GRIM_OK) {
-        uint8_t *h = slot->stage;
-        uint8_t *d = pool_base + off;
-        hipStream_t st = slot->stream;
-        SectionCopier cw{d, h, st}, cl{d, h, st}, ce{d, h, st}, cb{d, h, st};
-        uint64_t wbase = 0, rbase = 0, pbase = 0;
-        uint64_t *ro = reinterpret_cast<uint64_t *>(h + lay.read_off);
-        uint64_t *coff = reinterpret_cast<uint64_t *>(h + lay.cand_off);
-        for (auto &pt : take) {
-            Request &r = *pt.r;
-            const uint64_t nr = pt.rb - pt.ra, np = pt.pb - pt.pa;
-            cw.add(lay.words + wbase * 4, r.words() + pt.wlo, pt.nw * 4);
-            const uint64_t *sro = r.read_off(), *sco = r.cand_off();
-            const uint64_t shift = wbase * 16, base0 = pt.wlo * 16;
-            for (uint64_t i = 0; i < nr; ++i) {
-                ro[rbase + i] = sro[pt.ra + i] - base0 + shift;
-                coff[rbase + i] = sco[pt.ra + i] - pt.pa + pbase;
-            }
-            if (nr) {
-                cl.add(lay.read_len + rbase * 4, r.read_len() + pt.ra, nr * 4);
-                ce.add(lay.read_e + rbase * 4, r.read_e() + pt.ra, nr * 4);
-            }
-            if (np)
-                cb.add(lay.cand_bin + pbase * 4, r.cand_bin() + pt.pa, np * 4);
-            pt.fused_base = pbase;
-            wbase += pt.nw;
-            rbase += nr;
-            pbase += np;
-        }
-        coff[rbase] = pbase;
-        const uint32_t zero = 0;
-        cw.add(lay.words + wbase * 4, &zero, 4);  // trailing word read by tokens at the end
-        cw.flush();
-        cl.flush();
-        ce.flush();
-        cb.flush();
-        hipError_t e = cw.err != hipSuccess ? cw.err : cl.err != hipSuccess ? cl.err
-                     : ce.err != hipSuccess ? ce.err : cb.err;
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(d + lay.read_off, h + lay.read_off, rbase * 8,
-                               hipMemcpyHostToDevice, st);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(d + lay.cand_off, h + lay.cand_off, (rbase + 1) * 8,
-                               hipMemcpyHostToDevice, st);
-        if (e != hipSuccess)
-            rc = GRIM_E_HIP;
-        grim_batch_t b;
-        b.reads_2bit = reinterpret_cast<const uint32_t *>(d + lay.words);
-        b.n_read_words = wbase + 1;
-        b.read_off = reinterpret_cast<const uint64_t *>(d + lay.read_off);
-        b.read_len = reinterpret_cast<const uint32_t *>(d + lay.read_len);
-        b.read_e = reinterpret_cast<const uint32_t *>(d + lay.read_e);
-        b.e_den = e_den;
-        b.max_len = cfg.max_len;
-        b.cand_off = reinterpret_cast<const uint64_t *>(d + lay.cand_off);
-        b.cand_bin = reinterpret_cast<const uint32_t *>(d + lay.cand_bin);
-        b.n_reads = rbase;
-        b.n_pairs = pbase;
-        uint8_t *dout = d + lay.out_base;
-        uint8_t *hout = h + lay.out_base;
-        int32_t *dcounts = reinterpret_cast<int32_t *>(dout + lay.counts);
-        uint32_t *dbits = reinterpret_cast<uint32_t *>(dout + lay.bits);
-        if (rc == GRIM_OK)
-            rc = grim_filter_batch(idx, &b, dcounts, dbits, d + lay.ws, lay.ws_bytes, nullptr, st);
-        // results: large count slices straight into the request's result area,
-        // the rest (small slices, all pass bits, the status word) via the stage;
-        // no counts at all when only the pass bits are results
-        if (rc == GRIM_OK) {
-            const bool bits_only = (cfg.flags & GRIM_SERVE_PASS_BITS_ONLY) != 0;
-            uint64_t run_lo = 0, run_hi = 0;
-            bool run = false;
-            auto flush = [&] {
-                if (run && e == hipSuccess)
-                    e = hipMemcpyAsync(hout + run_lo, dout + run_lo, run_hi - run_lo,
-                                       hipMemcpyDeviceToHost, st);
-                run = false;
-            };
-            for (size_t j = 0; j < take.size() && e == hipSuccess && !bits_only; ++j) {
-                Part &pt = take[j];
-                const uint64_t lo = lay.counts + pt.fused_base * 4, nb = (pt.pb - pt.pa) * 4;
-                if (nb >= kDirectBytes) {
+        const bool bits_only = (cfg.flags & GRIM_SERVE_PASS_BITS_ONLY) != 0;
+        uint64_t run_lo = 0, run_hi = 0;
+        bool run = false;
+        auto flush = [&] {
+            if (run && e == GRIM_OK)
+                e = be.copy_d2h(hout + run_lo, dout + run_lo, run_hi - run_lo, st);
+            run = false;
+        };
+        for (size_t j = 0; j < take.size() && e == GRIM_OK && !bits_only; ++j) {
+            Part &pt = take[j];
+            const uint64_t lo = lay.counts + pt.fused_base * 4, nb = (pt.pb - pt.pa) * 4;
+            if (nb >= kDirectBytes) {
+                flush();
+                e = be.copy_d2h(pt.r->counts() + pt.pa, dout + lo, nb, st);
+                pt.counts_direct = true;
+            } else if (nb) {
+                if (run && lo == run_hi) {
+                    run_hi = lo + nb;
+                } else {
                     flush();
-                    e = hipMemcpyAsync(pt.r->counts() + pt.pa, dout + lo, nb,
-                                       hipMemcpyDeviceToHost, st);
-                    pt.counts_direct = true;
-                } else if (nb) {
-                    if (run && lo == run_hi) {
-                        run_hi = lo + nb;
-                    } else {
-                        flush();
-                        run = true;
-                        run_lo = lo;
-                        run_hi = lo + nb;
-                    }
+                    run = true;
+                    run_lo = lo;
+                    run_hi = lo + nb;
                 }
             }
-            flush();
-            if (e == hipSuccess)
-                e = hipMemcpyAsync(hout + lay.bits, dout + lay.bits, ((pbase + 31) / 32) * 4 + 4,
-                                   hipMemcpyDeviceToHost, st);
-            if (e == hipSuccess)  // status word of this launch
-                e = hipMemcpyAsync(hout + lay.status, d + lay.ws, 4, hipMemcpyDeviceToHost, st);
-            if (e == hipSuccess)
-                e = hipEventRecord(slot->done, st);
-            if (e != hipSuccess)
-                rc = GRIM_E_HIP;
         }
+        flush();
+        if (e == GRIM_OK)
+            e = be.copy_d2h(hout + lay.bits, dout + lay.bits, ((pbase + 31) / 32) * 4 + 4, st);
+        if (e == GRIM_OK)  // status word of this launch
+            e = be.copy_d2h(hout + lay.status, d + lay.ws, 4, st);
+        if (e != GRIM_OK)
+            rc = GRIM_E_HIP;
     }
     lk.lock();
-    if (rc != GRIM_OK) {
-        // the tick never completed on the device: fail its requests (a request
-        // with reads still queued is dropped from the queue)
-        (void)hipStreamSynchronize(slot->stream);
-        const auto t = Clock::now();
-        for (auto &pt : take) {
-            Request &r = *pt.r;
-            if (!r.all_admitted) {
-                drop_from_queue(r);
-                r.all_admitted = true;
-            }
-            r.status = rc;
-            part_closed(r, t);
-        }
-        pool->release(off, lay.total);
-        slot->busy = false;
-        if (--running_ticks == 0)
-            busy_s += std::chrono::duration<double>(t - busy_since).count();
-        cv_done.notify_all();
-    } else {
+    if (rc == GRIM_OK) {
         slot->parts = std::move(take);
+        // queued last, with the tick's parts in place: the notice may run at once
+        if (be.notify(st, on_tick_done, slot) == GRIM_OK)
+            return true;
+        rc = GRIM_E_HIP;
+        take = std::move(slot->parts);
+        slot->parts.clear();
     }
+    // the tick never completed on the device: fail its requests (a request
+    // with reads still queued is dropped from the queue)
+    (void)be.stream_sync(slot->stream);
+    const auto t = Clock::now();
+    for (auto &pt : take) {
+        Request &r = *pt.r;
+        if (!r.all_admitted) {
+            drop_from_queue(r);
+            r.all_admitted = true;
+        }
+        r.status = rc;
+        part_closed(r, t);
+    }
+    pool->release(off, lay.total);
+    slot->busy = false;
+    if (--running_ticks == 0)
+        busy_s += std::chrono::duration<double>(t - busy_since).count();
+    cv_done.notify_all();
     return true;
 }
 
 void grim_server::run()
 {
-    (void)hipSetDevice(device);
+    backend().set_device(device);
     std::unique_lock<std::mutex> lk(mu);
     for (;;) {
-        bool progress = false;
-        for (auto &s : slots) {
-            if (s.busy && hipEventQuery(s.done) == hipSuccess) {
-                retire(s);
-                progress = true;
-            }
+        uint64_t seen;
+        {
+            std::lock_guard<std::mutex> bl(bell_mu);
+            seen = bell;  // a ring after this point wakes the wait below
         }
+        for (auto &s : slots)
+            if (s->busy && s->finished.load(std::memory_order_acquire))
+                retire(*s);
         if (stop && running_ticks == 0)
             break;
         if (!stop)
-            while (launch_tick(lk))
-                progress = true;
-        if (!progress) {
-            if (running_ticks > 0)
-                cv_work.wait_for(lk, std::chrono::microseconds(50));
-            else
-                cv_work.wait_for(lk, std::chrono::milliseconds(5));
+            while (launch_tick(lk)) {
+            }
+        lk.unlock();
+        {
+            // a bounded sleep as well, measured on the system clock: its timed
+            // wait is the one every thread checker models
+            std::unique_lock<std::mutex> bl(bell_mu);
+            bell_cv.wait_until(bl, std::chrono::system_clock::now() + std::chrono::milliseconds(100),
+                               [&] { return bell != seen; });
         }
+        lk.lock();
     }
 }
+
+namespace {
+
+// Frees what grim_serve_create has set up so far (no scheduler thread yet).
+void free_server_parts(grim_server *s)
+{
+    const grim_serve::Backend &be = backend();
+    for (auto &sl : s->slots) {
+        if (sl->stream)
+            be.stream_destroy(sl->stream);
+        be.pinned_free(sl->stage);
+    }
+    be.pinned_free(s->arena);
+    be.device_free(s->pool_base);
+}
+
+}  // namespace
 
 extern "C" int grim_serve_create(const grim_index_t *idx, const grim_serve_cfg_t *cfg,
                                  grim_server_t **out)
@@ -795,42 +848,51 @@ extern "C" int grim_serve_create(const grim_index_t *idx, const grim_serve_cfg_t
         c.max_tick_pairs = 8u << 20;
     if (!c.max_len)
         c.max_len = 1024;
-    if (c.max_len > grim::kMaxLen || c.n_streams > 16 || (c.flags & ~GRIM_SERVE_PASS_BITS_ONLY))
+    if (c.max_len > GRIM_MAX_READ_LEN || c.n_streams > 16 ||
+        (c.flags & ~GRIM_SERVE_PASS_BITS_ONLY))
         return GRIM_E_INVALID;
+    const grim_serve::Backend &be = backend();
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev != idx->device)
+    if (be.current_device(&dev) != GRIM_OK || dev != be.index_device(idx))
         return GRIM_E_INVALID;
     auto s = std::make_unique<grim_server>();
     s->idx = idx;
     s->cfg = c;
     s->device = dev;
-    if (hipMalloc(reinterpret_cast<void **>(&s->pool_base), c.hbm_budget_bytes) != hipSuccess)
+    if (be.device_alloc(c.hbm_budget_bytes, &s->pool_base) != GRIM_OK)
         return GRIM_E_NOMEM;
     s->pool = std::make_unique<Pool>(c.hbm_budget_bytes);
     // pinned arena for request blocks: as large as the device budget, at most 4 GiB
     s->arena_bytes = std::min<uint64_t>(std::max<uint64_t>(c.hbm_budget_bytes, 64ull << 20),
                                         4ull << 30);
-    if (hipHostMalloc(reinterpret_cast<void **>(&s->arena), s->arena_bytes, hipHostMallocDefault) !=
-        hipSuccess) {
+    if (be.pinned_alloc(s->arena_bytes, &s->arena) != GRIM_OK) {
         s->arena = nullptr;
         s->arena_bytes = 0;
     }
     s->arena_pool = std::make_unique<Pool>(s->arena_bytes);
+    // every slot's staging buffer, sized once for the largest tick it stages:
+    // max(max_tick_pairs, 2^20) pairs, max(4096, pairs / 32) reads of max_len
+    // bases (admission keeps every tick's layout within it; a single read that
+    // alone would not fit is refused at submit)
+    const uint64_t P = std::max<uint64_t>(c.max_tick_pairs, 1ull << 20);
+    const uint64_t R = std::max<uint64_t>(4096, P / 32);
+    const uint64_t W = R * (c.max_len / 16 + 2) + 1;
+    s->stage_bytes = std::min<uint64_t>(c.hbm_budget_bytes, plan(W, R, P, ws_need(idx, P)).total);
     s->slots.resize(c.n_streams);
     for (auto &sl : s->slots) {
-        if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess) {
-            for (auto &x : s->slots) {
-                if (x.stream)
-                    (void)hipStreamDestroy(x.stream);
-                if (x.done)
-                    (void)hipEventDestroy(x.done);
-            }
-            if (s->arena)
-                (void)hipHostFree(s->arena);
-            (void)hipFree(s->pool_base);
+        sl = std::make_unique<Slot>();
+        sl->srv = s.get();
+        if (be.stream_create(&sl->stream) != GRIM_OK) {
+            sl->stream = nullptr;
+            free_server_parts(s.get());
             return GRIM_E_HIP;
         }
+        if (be.pinned_alloc(s->stage_bytes, &sl->stage) != GRIM_OK) {
+            sl->stage = nullptr;
+            free_server_parts(s.get());
+            return GRIM_E_NOMEM;
+        }
+        sl->stage_bytes = s->stage_bytes;
     }
     grim_server *raw = s.release();
     raw->thr = std::thread([raw] { raw->run(); });
@@ -867,6 +929,16 @@ int validate_request(const grim_server_t *s, const grim_batch_t *b)
     const uint64_t nwords = n ? b->n_read_words : 0;
     if (plan(nwords + 1, n, P, ws_need(s->idx, P)).total > s->cfg.hbm_budget_bytes)
         return GRIM_E_BUDGET;
+    // a read with more candidates than a tick holds runs alone in a tick: it
+    // must fit the staging buffer by itself
+    for (uint64_t i = 0; i < n; ++i) {
+        const uint64_t np = b->cand_off[i + 1] - b->cand_off[i];
+        if (np <= s->cfg.max_tick_pairs)
+            continue;
+        const uint64_t nw = ((b->read_off[i] + b->read_len[i] + 15) >> 4) - (b->read_off[i] >> 4);
+        if (plan(nw + 1, 1, np, ws_need(s->idx, np)).total > s->stage_bytes)
+            return GRIM_E_BUDGET;
+    }
     return GRIM_OK;
 }
 
@@ -883,7 +955,7 @@ int enqueue_request(grim_server_t *s, std::shared_ptr<Request> r, uint64_t *tick
         s->queue.push_back(r);
         ++s->submitted;
     }
-    s->cv_work.notify_one();
+    s->ring();
     *ticket = r->ticket;
     return GRIM_OK;
 }
@@ -1027,7 +1099,8 @@ extern "C" int grim_serve_wait(grim_server_t *s, uint64_t ticket, int64_t timeou
     auto done = [&] { return req->state == State::Done; };
     if (timeout_ms < 0)
         s->cv_done.wait(lk, done);
-    else if (!s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), done))
+    else if (!s->cv_done.wait_until(
+                 lk, std::chrono::system_clock::now() + std::chrono::milliseconds(timeout_ms), done))
         return GRIM_E_TIMEOUT;
     it = s->all.find(ticket);
     if (it == s->all.end())
@@ -1125,21 +1198,17 @@ extern "C" void grim_serve_destroy(grim_server_t *s)
         }
         s->queue.clear();
     }
-    s->cv_work.notify_all();
+    s->ring();
     if (s->thr.joinable())
         s->thr.join();
+    // every tick has been retired; wait until the streams (and the completion
+    // notices on them) have finished before the server's memory goes
+    const grim_serve::Backend &be = backend();
+    for (auto &sl : s->slots)
+        (void)be.stream_sync(sl->stream);
     for (auto &kv : s->all)
         s->free_block(*kv.second);
     s->all.clear();
-    for (auto &sl : s->slots) {
-        (void)hipStreamSynchronize(sl.stream);
-        if (sl.stage)
-            (void)hipHostFree(sl.stage);
-        (void)hipEventDestroy(sl.done);
-        (void)hipStreamDestroy(sl.stream);
-    }
-    if (s->arena)
-        (void)hipHostFree(s->arena);
-    (void)hipFree(s->pool_base);
+    free_server_parts(s);
     delete s;
 }

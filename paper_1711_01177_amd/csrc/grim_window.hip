@@ -8,7 +8,8 @@
 // Token-major copy of the index: row t holds bit b = "token t occurs in bin b"
 // for every bin (ceil(n_bins / 1024) * 32 words per row, zero past the last
 // bin, plus one pad word at the end of the buffer).  For a (read, window) each thread owns 32 consecutive
-// bins of the window (two adjacent row words joined by a funnel shift) and
+// bins of the window (one row word when the window starts on a multiple of 32
+// bins, else two adjacent row words joined by a funnel shift) and
 // adds, for every token position of the read, that token's bits into a
 // bit-sliced counter (carry-save adders), so repeated tokens count once per
 // position.  Each token costs one coalesced row segment for the whole window.
@@ -195,6 +196,44 @@ __device__ __forceinline__ uint32_t row_bins(__amdgpu_buffer_rsrc_t rs, uint32_t
     return __builtin_amdgcn_alignbit(v[1], v[0], sh);
 }
 
+// Bins lo + 32j + i of a token row when lo is a multiple of 32: one row word.
+__device__ __forceinline__ uint32_t row_word(const char *__restrict__ row, uint32_t byte_off)
+{
+    return *reinterpret_cast<const uint32_t *>(row + byte_off);
+}
+
+__device__ __forceinline__ uint32_t row_word(__amdgpu_buffer_rsrc_t rs, uint32_t byte_off)
+{
+    return __builtin_amdgcn_raw_buffer_load_b32(rs, byte_off, 0, 0);
+}
+
+// Adds the row bits of tokens [i0, i1) for one column into its counter.
+// ALIGNED: the window starts on a row word (sh = 0), so a column is one word
+// of each row and a wavefront's loads cover whole 256-byte runs.
+template <int NP, bool OFF32, bool ALIGNED>
+__device__ __forceinline__ void add_rows(SlicedCount<NP> &c, const uint32_t *toks, uint32_t i0,
+                                         uint32_t i1, __amdgpu_buffer_rsrc_t rs,
+                                         const char *__restrict__ rows, uint64_t row_bytes,
+                                         uint32_t bo, uint32_t sh)
+{
+    auto load = [&](uint32_t tk) -> uint32_t {
+        if (OFF32)
+            return ALIGNED ? row_word(rs, tk + bo) : row_bins(rs, tk + bo, sh);
+        const char *row = rows + (uint64_t)tk * row_bytes;
+        return ALIGNED ? row_word(row, bo) : row_bins(row, bo, sh);
+    };
+    uint32_t i = i0;
+    for (; i + 16 <= i1; i += 16) {
+        uint32_t w[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+            w[u] = load(toks[i + u]);
+        c.add16(w);
+    }
+    for (; i < i1; ++i)
+        c.add(load(toks[i]));
+}
+
 // One workgroup per read (reads taken from an atomic counter); the window of
 // read r is bins [win_lo[r], win_lo[r] + size) with size = cand_off[r+1] -
 // cand_off[r], and pair cand_off[r] + j is bin win_lo[r] + j.  Column j of a
@@ -273,24 +312,10 @@ __global__ __launch_bounds__(256) void window_kernel(WindowArgs a)
             c.clear();
             if (j < n_cols && wi < a.row_words) {
                 const uint32_t bo = (uint32_t)(wi * 4);
-                uint32_t i = i0;
-                for (; i + 16 <= i1; i += 16) {
-                    uint32_t w[16];
-#pragma unroll
-                    for (int u = 0; u < 16; ++u) {
-                        if (OFF32)
-                            w[u] = row_bins(rs, toks[i + u] + bo, sh);
-                        else
-                            w[u] = row_bins(rows + (uint64_t)toks[i + u] * row_bytes, bo, sh);
-                    }
-                    c.add16(w);
-                }
-                for (; i < i1; ++i) {
-                    if (OFF32)
-                        c.add(row_bins(rs, toks[i] + bo, sh));
-                    else
-                        c.add(row_bins(rows + (uint64_t)toks[i] * row_bytes, bo, sh));
-                }
+                if (sh == 0)
+                    add_rows<NP, OFF32, true>(c, toks, i0, i1, rs, rows, row_bytes, bo, sh);
+                else
+                    add_rows<NP, OFF32, false>(c, toks, i0, i1, rs, rows, row_bytes, bo, sh);
             }
             if (half == 1) {
 #pragma unroll

@@ -14,6 +14,7 @@ import sys
 import numpy as np
 import pytest
 
+import bench
 import grim_synth as gs
 import oracle
 from tests.gpu_helpers import assert_same, lib
@@ -242,8 +243,8 @@ def test_fullsize_served_requests(full):
 
 def test_fullsize_windows_sampled_and_properties(full):
     """The bin-window leg as bench.py runs it: the batched 3.1 Gbp index, its
-    token-major copy, the first 200,000 reads each against the 4096 bins centred
-    on its true bin.  Sampled pairs against the oracle one by one; over every
+    token-major copy, the first 200,000 reads each against a 4096-bin window
+    around its true bin that starts on a multiple of 1024 bins.  Sampled pairs against the oracle one by one; over every
     pair, 0 <= count <= ntok and pass == (count >= T); every true bin passes."""
     import torch
     if full["name"] != "batched":
@@ -253,7 +254,8 @@ def test_fullsize_windows_sampled_and_properties(full):
     n_reads, wbins = 200_000, 4096
     nb = idx.n_bins
     tb = (w["read_z"][:n_reads] // w["B"]).astype(np.int64)
-    lo = np.clip(tb - wbins // 2, 0, nb - wbins).astype(np.int64)
+    lo = bench.window_lo(tb, nb, wbins, 1024).astype(np.int64)
+    assert np.all((tb >= lo) & (tb - lo < wbins))  # the gather index below stays in range
     off = np.arange(n_reads + 1, dtype=np.uint64) * wbins
     o_end = int(w["read_off"][n_reads - 1]) + int(w["read_len"][n_reads - 1])
     wb = g.Batch(w["codes"][:o_end], w["read_off"][:n_reads], w["read_len"][:n_reads],

@@ -110,8 +110,9 @@ def test_transpose_layout(q, G, B):
 
 def test_windows_token_blocks_and_many_reads():
     """Token counts around the 16-token blocks of the counter (ntok 0 ... 70,
-    including reads shorter than q), windows of every alignment and size up
-    to 9,000 bins, and more reads than the persistent grid has workgroups."""
+    including reads shorter than q), windows of every alignment (a quarter of
+    them on multiples of 32 bins) and size up to 9,000 bins, and more reads
+    than the persistent grid has workgroups."""
     g = lib()
     q, B, O = 5, 150, 110
     ref = gs.reference(61, 1_200_000, 0.3, 30, 300, 0.85, 0.98)
@@ -129,6 +130,8 @@ def test_windows_token_blocks_and_many_reads():
     sizes = rng.choice([1, 5, 31, 32, 33, 63, 64, 65, 127, 128, 129, 4095, 4096, 4097, 9000],
                        size=n)
     win_lo = rng.integers(0, nb, size=n)
+    win_lo[::4] = (win_lo[::4] // 32) * 32      # windows on a row word: the one-word path
+    win_lo[::16] = (win_lo[::16] // 1024) * 1024
     w = window_workload(ref, q, B, O, reads, e_nums, win_lo, sizes)
     idx = g.grim_build_bins(ref, q, B, O)
     idx.transpose()
