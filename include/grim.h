@@ -55,6 +55,7 @@ extern "C" {
 #define GRIM_E_TIMEOUT (-10)      /* serving: wait timed out                    */
 #define GRIM_E_READ (-11)         /* a read longer than max_len or outside the  */
                                   /* packed buffer, or inconsistent cand_off    */
+#define GRIM_E_SCRATCH (-12)      /* batch too large for the static scratch     */
 
 /* Bits of the device status word that the filter kernels set. */
 #define GRIM_FLAG_BIN_RANGE 1u    /* some pair had bin id >= n_bins            */
@@ -194,6 +195,31 @@ int grim_workspace_size(const grim_index_t *idx, uint64_t n_pairs, const grim_tu
 int grim_filter_batch(const grim_index_t *idx, const grim_batch_t *b, int32_t *counts,
                       uint32_t *pass_bits, void *workspace, uint64_t workspace_bytes,
                       const grim_tuning_t *tune, void *stream);
+
+/* The batched filter for callers that cannot allocate device memory at all:
+ * code being captured into a HIP graph, tight serving loops, and harnesses
+ * that forbid allocation.  Same computation, outputs and tuning as
+ * grim_filter_batch, but no workspace argument: the scratch (tile counter and
+ * the tile -> first read table) lives in a file-scope device array of
+ * GRIM_NOALLOC_SCRATCH_BYTES per GPU, which the library holds from its first
+ * use on a device until the process ends.  The call allocates nothing (no
+ * hipMalloc, hipFree or allocating library routine) and is asynchronous on
+ * `stream`.
+ *   status: device uint32_t owned by the caller; the kernels reset it and set
+ *           the GRIM_FLAG_* bits of this call in it (grim_filter_status may be
+ *           called with status as its workspace argument).
+ * Limit: the scratch holds 256 + 4 * ceil(n_pairs / tile_pairs) bytes; a batch
+ * that needs more (about 2.1e9 pairs at tile_pairs 512, 4.3e9 at 1024) gives
+ * GRIM_E_SCRATCH before anything is queued.  Every call on one GPU shares that
+ * GPU's scratch: calls whose kernels overlap on one GPU (on different streams
+ * or threads) race and must not be issued; calls queued one after another on
+ * one stream are fine (each resets what must start at zero).
+ * Errors: as grim_filter_batch, GRIM_E_INVALID for a NULL status, and
+ * GRIM_E_SCRATCH. */
+#define GRIM_NOALLOC_SCRATCH_BYTES (16u << 20)
+int grim_filter_batch_noalloc(const grim_index_t *idx, const grim_batch_t *b, int32_t *counts,
+                              uint32_t *pass_bits, uint32_t *status, const grim_tuning_t *tune,
+                              void *stream);
 
 /* The same filter, plain form: one workgroup per read, no persistence, no
  * tuning, no work list (the straightforward per-read launch the batched form

@@ -43,6 +43,8 @@ GRIM_E_UNSUPPORTED = -8
 GRIM_E_IO = -9
 GRIM_E_TIMEOUT = -10
 GRIM_E_READ = -11
+GRIM_E_SCRATCH = -12
+GRIM_NOALLOC_SCRATCH_BYTES = 16 << 20
 GRIM_FLAG_BIN_RANGE = 1
 GRIM_FLAG_READ = 2
 GRIM_SERVE_PASS_BITS_ONLY = 1
@@ -127,6 +129,8 @@ _SIGS = {
     "grim_workspace_size": (ctypes.c_int, [_vp, _u64, _P(grim_tuning_t), _P(_u64)]),
     "grim_filter_batch": (ctypes.c_int, [_vp, _P(grim_batch_t), _vp, _vp, _vp, _u64,
                                          _P(grim_tuning_t), _vp]),
+    "grim_filter_batch_noalloc": (ctypes.c_int, [_vp, _P(grim_batch_t), _vp, _vp, _vp,
+                                                 _P(grim_tuning_t), _vp]),
     "grim_filter_plain": (ctypes.c_int, [_vp, _P(grim_batch_t), _vp, _vp, _vp, _u64, _vp]),
     "grim_filter_status": (ctypes.c_int, [_vp, _vp, _P(_u32)]),
     "grim_tune": (ctypes.c_int, [_vp, _P(grim_batch_t), _vp, _vp, _vp, _u64, _vp,
@@ -405,6 +409,16 @@ def grim_filter_batch(index, batch, counts, pass_bits, workspace, tune=None, str
                                   _ptr(pass_bits), _ptr(workspace), workspace.numel(),
                                   ctypes.byref(tune) if tune is not None else None,
                                   _stream(stream)), "grim_filter_batch")
+
+
+def grim_filter_batch_noalloc(index, batch, counts, pass_bits, status, tune=None, stream=None):
+    """The batched filter with the library's static scratch (no workspace, no
+    allocation); status is a device tensor of at least 4 bytes that receives
+    the call's GRIM_FLAG_* bits."""
+    _check(_lib.grim_filter_batch_noalloc(index.handle, ctypes.byref(batch.c), _ptr(counts),
+                                          _ptr(pass_bits), _ptr(status),
+                                          ctypes.byref(tune) if tune is not None else None,
+                                          _stream(stream)), "grim_filter_batch_noalloc")
 
 
 def grim_filter_plain(index, batch, counts, pass_bits, workspace, stream=None):

@@ -236,6 +236,9 @@ extern "C" const char *grim_strerror(int code)
     case GRIM_E_IO: return "index file error";
     case GRIM_E_TIMEOUT: return "timed out";
     case GRIM_E_READ: return "invalid read or candidate offsets";
+    case GRIM_E_SCRATCH:
+        return "batch needs more than the static scratch holds (use grim_filter_batch with a "
+               "workspace)";
     default: return "unknown error";
     }
 }
@@ -528,6 +531,58 @@ extern "C" int grim_filter_batch(const grim_index_t *idx, const grim_batch_t *b,
         return rc;
     return enqueue_batched(idx, b, counts, pass_bits, workspace, workspace_bytes, t,
                            reinterpret_cast<hipStream_t>(stream));
+}
+
+// ------------------------------------------------- filter without allocation
+// The scratch of grim_filter_batch_noalloc: one file-scope device array per GPU
+// (tile counter, padded header, first read of each tile).  Host code never uses
+// the array's name as an address: the device address comes from
+// hipGetSymbolAddress, once per device, and is kept in g_scratch_ptr.
+static __device__ __align__(256) uint8_t scratch[GRIM_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, void *> g_scratch_ptr;
+
+int scratch_address(int dev, void **out)
+{
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it != g_scratch_ptr.end()) {
+        *out = it->second;
+        return GRIM_OK;
+    }
+    void *p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p || (reinterpret_cast<uintptr_t>(p) & 255))
+        return hip_fail(hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[dev] = p;
+    *out = p;
+    return GRIM_OK;
+}
+}  // namespace
+
+extern "C" int grim_filter_batch_noalloc(const grim_index_t *idx, const grim_batch_t *b,
+                                         int32_t *counts, uint32_t *pass_bits, uint32_t *status,
+                                         const grim_tuning_t *tune, void *stream)
+{
+    int rc = check_batch(idx, b);
+    if (rc)
+        return rc;
+    if (!status)
+        return GRIM_E_INVALID;
+    grim_tuning_t t;
+    rc = resolve_tuning(idx, b->max_len, tune, &t);
+    if (rc)
+        return rc;
+    if (ws_bytes_for(b->n_pairs, t.tile_pairs) > GRIM_NOALLOC_SCRATCH_BYTES)
+        return GRIM_E_SCRATCH;
+    void *ws = nullptr;
+    rc = scratch_address(idx->device, &ws);  // check_batch made idx->device current
+    if (rc)
+        return rc;
+    return enqueue_batched(idx, b, counts, pass_bits, ws, GRIM_NOALLOC_SCRATCH_BYTES, t,
+                           reinterpret_cast<hipStream_t>(stream), status);
 }
 
 extern "C" int grim_filter_plain(const grim_index_t *idx, const grim_batch_t *b, int32_t *counts,

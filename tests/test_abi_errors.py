@@ -28,6 +28,8 @@ def test_null_handles_are_rejected(g):
     assert L.grim_workspace_size(None, 10, None, ctypes.byref(u64)) == INV
     assert L.grim_filter_batch(None, ctypes.byref(b), None, None, None, 0, None, None) == INV
     assert L.grim_filter_plain(None, ctypes.byref(b), None, None, None, 0, None) == INV
+    assert L.grim_filter_batch_noalloc(None, ctypes.byref(b), None, None, None, None, None) == INV
+    assert g.grim_strerror(g.GRIM_E_SCRATCH).startswith("batch needs more than the static scratch")
     assert L.grim_filter_status(None, None, None) == INV
     assert L.grim_survivors_workspace_size(10, None) == INV
     assert L.grim_compact_survivors(None, None, 0, None, None, None, None, None, 0, None) == INV
