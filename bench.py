@@ -215,6 +215,7 @@ def serving_leg(g, idx, w, rng, loads=(0.25, 0.5, 0.75, 0.9), n_requests=10_000,
     # whole pool submitted at once, twice (each buffer is in flight at most once
     # at a time), pairs over the mean wall time
     drain([submit(hb) for hb in reqs])
+    srv.stats(reset=True)
     walls = []
     for _ in range(2):
         t0 = time.perf_counter()
@@ -222,6 +223,8 @@ def serving_leg(g, idx, w, rng, loads=(0.25, 0.5, 0.75, 0.9), n_requests=10_000,
         walls.append(time.perf_counter() - t0)
     capacity = sum(hb.n_pairs for hb in reqs) / float(np.mean(walls))
     cap_stats = srv.stats(reset=True)
+    # scheduler thread time during the two bursts, against their wall time
+    sched_busy = (cap_stats["sched_launch_s"] + cap_stats["sched_retire_s"]) / max(1e-9, sum(walls))
     checked = None
     if expect is not None and inplace and not bits_only:
         # every pool request's results, as the capacity bursts left them, against
@@ -254,6 +257,7 @@ def serving_leg(g, idx, w, rng, loads=(0.25, 0.5, 0.75, 0.9), n_requests=10_000,
                capacity_burst_s=walls,
                capacity_pairs_per_s=capacity,
                capacity_ticks=cap_stats["ticks"],
+               capacity_scheduler_busy=sched_busy,
                results_checked=checked,
                link_bytes_per_pair=dict(up=up_bytes / n_pairs_all, down=down_bytes / n_pairs_all),
                points=[])
@@ -297,6 +301,8 @@ def serving_leg(g, idx, w, rng, loads=(0.25, 0.5, 0.75, 0.9), n_requests=10_000,
                                   mean_ms=st["mean_ms"], max_ms=st["max_ms"],
                                   pairs_per_s=st["pairs_done"] / wall,
                                   mean_requests_per_tick=st["mean_requests_per_tick"],
+                                  sched_launch_s=st["sched_launch_s"],
+                                  sched_retire_s=st["sched_retire_s"],
                                   ticks=st["ticks"],
                                   arrivals_delayed_by_full_pool=late))
     srv.destroy()

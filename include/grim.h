@@ -357,7 +357,9 @@ void grim_seed_index_free(grim_seed_index_t *si);
  * offsets 0, k, 2k, ... while the seed fits; every occurrence p of the seed at
  * offset o proposes location z = p - o clamped into [0, G - 1] and bin
  * z / bin_stride; a read's bins are deduplicated, sorted increasingly and cut
- * to the first `cap`.  Reads outside the packed buffer get no candidates.
+ * to the first `cap`.  Reads outside the packed buffer, and reads longer than
+ * reads->max_len when it is not 0, get no candidates.  Calls on one seed index
+ * take turns (the index keeps its device temporaries between calls).
  * Synchronous; allocates the result (CSR offsets n_reads + 1 u64, bins u32) on
  * the device.  GRIM_E_UNSUPPORTED beyond 2^31 - 1 seed hits or reads. */
 int grim_seed_candidates(const grim_seed_index_t *si, const grim_batch_t *reads,
@@ -435,6 +437,8 @@ typedef struct grim_serve_stats {
     double pairs_per_s;       /* pairs_done / busy_s                                */
     uint64_t peak_device_bytes;
     double mean_requests_per_tick;
+    double sched_launch_s;    /* scheduler thread time spent staging and queueing ticks */
+    double sched_retire_s;    /* scheduler thread time spent handing results back       */
 } grim_serve_stats_t;
 
 /* Create a server on the current device.  It allocates its device pool

@@ -104,7 +104,8 @@ class grim_serve_stats_t(ctypes.Structure):
                 ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
                 ("max_ms", ctypes.c_double), ("busy_s", ctypes.c_double),
                 ("pairs_per_s", ctypes.c_double), ("peak_device_bytes", _u64),
-                ("mean_requests_per_tick", ctypes.c_double)]
+                ("mean_requests_per_tick", ctypes.c_double), ("sched_launch_s", ctypes.c_double),
+                ("sched_retire_s", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

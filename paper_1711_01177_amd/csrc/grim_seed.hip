@@ -4,15 +4,21 @@
 // Fig. 1, and Section "Integration with a Full Read Mapper").
 //
 // Index: counts of every k-mer (atomic histogram), exclusive scan into
-// offsets, scatter of positions.  Candidates: per read, the number of hits of
-// its seeds (k-mers at offsets 0, k, 2k, ...), a scan, the hit bins
-// (clamp(p - o) / B), a segmented radix sort per read (hipCUB), and a per-read
-// dedup + cap pass that writes the CSR candidate list.
+// offsets, scatter of positions.  Candidates, in passes that each keep many
+// independent memory accesses in flight:
+//   1. per read: its seeds (k-mers at offsets 0, k, 2k, ...) as (read, seed)
+//      items, each with its index range (first position, hit count);
+//   2. a scan of the items' hit counts lays all hits out read by read;
+//   3. per 64 items: the wavefront copies the items' hits, converted to bins
+//      (clamp(p - o) / B), to their places (flat, all lanes busy);
+//   4. per read: sort its bins (in registers up to 64, in LDS up to 2048, in
+//      place in global memory beyond), keep the distinct ones up to the cap;
+//   5. a scan of the list lengths and a copy pass write the CSR candidates.
 #include <hip/hip_runtime.h>
-#include <hipcub/hipcub.hpp>
 
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "grim_internal.h"
@@ -23,10 +29,16 @@ struct grim_seed_index {
     uint64_t G;
     uint64_t *d_off;   // 4^k + 1 offsets into d_pos
     uint32_t *d_pos;   // G - k + 1 positions grouped by k-mer
+    // device temporaries of grim_seed_candidates, kept between calls (grown
+    // when a batch needs more); calls on one seed index take turns on mu
+    std::mutex mu;
+    uint8_t *tmp[3] = {nullptr, nullptr, nullptr};
+    uint64_t tmp_bytes[3] = {0, 0, 0};
 };
 
 struct grim_candidates {
     uint64_t n_reads, n_pairs;
+    uint8_t *buf;      // one allocation: the offsets, then the bins
     uint64_t *d_off;   // n_reads + 1
     uint32_t *d_bin;   // n_pairs (at least one element)
 };
@@ -174,116 +186,355 @@ __global__ __launch_bounds__(256) void scan_apply_kernel(const T *__restrict__ i
 }
 
 // --------------------------------------------------------------- seeding
-__global__ __launch_bounds__(256) void seed_count_kernel(
-    const uint32_t *__restrict__ rw, uint64_t nw, const uint64_t *__restrict__ read_off,
-    const uint32_t *__restrict__ read_len, uint64_t n_reads, uint32_t k,
-    const uint64_t *__restrict__ idx_off, uint64_t *__restrict__ hits)
+// Number of seeds of each read (0 for a read outside the packed buffer or, when
+// max_len > 0, longer than max_len).
+__global__ __launch_bounds__(256) void seed_nseeds_kernel(const uint64_t *__restrict__ read_off,
+                                                          const uint32_t *__restrict__ read_len,
+                                                          uint64_t n_reads, uint64_t nw, uint32_t k,
+                                                          uint32_t max_len,
+                                                          uint32_t *__restrict__ nseeds)
 {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     const uint64_t nb = nw * 16;
     for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n_reads; r += stride) {
         const uint32_t L = read_len[r];
         const uint64_t off = read_off[r];
-        uint64_t s = 0;
-        if (off <= nb && L <= nb - off) {
-            for (uint32_t o = 0; o + k <= L; o += k) {
-                const uint32_t km = kmer_at(rw, nw, off + o, k);
-                s += idx_off[km + 1] - idx_off[km];
-            }
-        }
-        hits[r] = s;
+        const bool ok = off <= nb && L <= nb - off && L >= k && (max_len == 0 || L <= max_len);
+        nseeds[r] = ok ? L / k : 0u;
     }
 }
 
-// One wavefront per read; its seeds are looked up 8 at a time, one group of 8
-// lanes per seed, and each group copies its seed's hits (seed order, then index
-// order, as the count pass assumed) to the read's hit range.
-constexpr int kSeedGroup = 8;                 // lanes per seed
-constexpr int kSeedsPerStep = kWave / kSeedGroup;
-
-__global__ __launch_bounds__(256) void seed_emit_kernel(
+// One thread per read: its seeds' items at item_base[r] + s (index range start
+// a, hit count, seed offset o = s * k in the read).
+__global__ __launch_bounds__(256) void seed_items_kernel(
     const uint32_t *__restrict__ rw, uint64_t nw, const uint64_t *__restrict__ read_off,
-    const uint32_t *__restrict__ read_len, uint64_t n_reads, uint32_t k,
-    const uint64_t *__restrict__ idx_off, const uint32_t *__restrict__ idx_pos, uint64_t G,
-    uint64_t B, const uint64_t *__restrict__ hit_off, uint32_t *__restrict__ hit_bin)
+    const uint64_t *__restrict__ item_base, uint64_t n_reads, uint32_t k,
+    const uint64_t *__restrict__ idx_off, uint32_t *__restrict__ item_a,
+    uint32_t *__restrict__ item_cnt, uint32_t *__restrict__ item_o)
 {
-    const int lane = threadIdx.x & 63, grp = lane / kSeedGroup, sub = lane % kSeedGroup;
-    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n_reads; r += stride) {
+        const uint64_t i0 = item_base[r], ns = item_base[r + 1] - i0;
+        const uint64_t off = read_off[r];
+        for (uint64_t s = 0; s < ns; ++s) {
+            const uint32_t km = kmer_at(rw, nw, off + s * k, k);
+            const uint64_t a = idx_off[km];
+            item_a[i0 + s] = (uint32_t)a;
+            item_cnt[i0 + s] = (uint32_t)(idx_off[km + 1] - a);
+            item_o[i0 + s] = (uint32_t)(s * k);
+        }
+    }
+}
+
+// The same items in a fixed layout, one thread per item: item i is seed
+// i % S of read i / S, S = max_len / k seeds per read (a read longer than
+// max_len gets no seeds).
+__global__ __launch_bounds__(256) void seed_items_fixed_kernel(
+    const uint32_t *__restrict__ rw, uint64_t nw, const uint64_t *__restrict__ read_off,
+    const uint32_t *__restrict__ read_len, uint64_t n_items, uint32_t S, uint32_t max_len,
+    uint32_t k, const uint64_t *__restrict__ idx_off, uint32_t *__restrict__ item_a,
+    uint32_t *__restrict__ item_cnt, uint32_t *__restrict__ item_o)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     const uint64_t nb = nw * 16;
-    for (uint64_t r = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); r < n_reads;
-         r += waves) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_items; i += stride) {
+        const uint64_t r = i / S;
+        const uint32_t sd = (uint32_t)(i - r * S);
         const uint32_t L = read_len[r];
         const uint64_t off = read_off[r];
-        if (off > nb || L > nb - off)
-            continue;
-        const uint32_t n_seeds = L >= k ? L / k : 0u;
-        uint64_t dst = hit_off[r];
-        for (uint32_t s0 = 0; s0 < n_seeds; s0 += kSeedsPerStep) {
-            const uint32_t sd = s0 + (uint32_t)grp;
-            const uint32_t o = sd * k;
-            uint64_t a = 0, cnt = 0;
-            if (sd < n_seeds) {
-                const uint32_t km = kmer_at(rw, nw, off + o, k);
-                a = idx_off[km];
-                cnt = idx_off[km + 1] - a;
-            }
-            // exclusive prefix of the groups' hit counts (lane sub == 0 of each group)
-            uint64_t incl = sub == 0 ? cnt : 0;
-#pragma unroll
-            for (int d = 1; d < kWave; d <<= 1) {
-                const uint64_t y = __shfl_up(incl, d);
-                if (lane >= d)
-                    incl += y;
-            }
-            const uint64_t total = __shfl(incl, kWave - 1);
-            const uint64_t before = incl - (sub == 0 ? cnt : 0);
-            // the group's first lane holds its exclusive offset
-            const uint64_t gdst = dst + __shfl(before, grp * kSeedGroup);
-            for (uint64_t h = sub; h < cnt; h += kSeedGroup) {
-                int64_t z = (int64_t)idx_pos[a + h] - (int64_t)o;
-                if (z < 0)
-                    z = 0;
-                if ((uint64_t)z > G - 1)
-                    z = (int64_t)(G - 1);
-                hit_bin[gdst + h] = (uint32_t)((uint64_t)z / B);
-            }
-            dst += total;
+        uint64_t a = 0, cnt = 0;
+        if (off <= nb && L <= nb - off && L <= max_len && (uint64_t)(sd + 1) * k <= L) {
+            const uint32_t km = kmer_at(rw, nw, off + (uint64_t)sd * k, k);
+            a = idx_off[km];
+            cnt = idx_off[km + 1] - a;
         }
+        item_a[i] = (uint32_t)a;
+        item_cnt[i] = (uint32_t)cnt;
+        item_o[i] = sd * k;
     }
 }
 
-// one wavefront per read: number of distinct bins in the sorted segment, capped
-template <bool EMIT>
-__global__ __launch_bounds__(256) void unique_kernel(const uint32_t *__restrict__ sorted,
-                                                     const uint64_t *__restrict__ seg_off,
-                                                     uint64_t n_reads, uint32_t cap,
-                                                     uint64_t *__restrict__ count,
-                                                     const uint64_t *__restrict__ out_off,
-                                                     uint32_t *__restrict__ out)
+// hit_off[r] = item_off[item_base[r]] (item_base null: r * S) for r <= n_reads;
+// thread 0 also clears the long-list counter.
+__global__ __launch_bounds__(256) void seed_hit_off_kernel(const uint64_t *__restrict__ item_base,
+                                                           uint64_t S,
+                                                           const uint64_t *__restrict__ item_off,
+                                                           uint64_t n_reads,
+                                                           uint64_t *__restrict__ hit_off,
+                                                           uint32_t *__restrict__ long_count)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i0 == 0)
+        *long_count = 0u;
+    for (uint64_t r = i0; r <= n_reads; r += stride)
+        hit_off[r] = item_off[item_base ? item_base[r] : r * S];
+}
+
+// One wavefront per 64 consecutive items: every lane takes one hit at a time
+// of the items' hit range (its item found by a binary search over the lanes'
+// offsets), four loads in flight per lane, and writes the hit's bin at its
+// place.  Works whatever the items' hit counts (a single item may hold most of
+// the range).
+__global__ __launch_bounds__(256) void seed_emit_kernel(
+    const uint32_t *__restrict__ item_a, const uint32_t *__restrict__ item_o,
+    const uint64_t *__restrict__ item_off, uint64_t n_items,
+    const uint32_t *__restrict__ idx_pos, uint64_t G, uint64_t B, uint32_t *__restrict__ hb)
 {
     const int lane = threadIdx.x & 63;
     const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
-    const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
-    for (uint64_t r = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); r < n_reads;
-         r += waves) {
-        const uint64_t a = seg_off[r], b = seg_off[r + 1];
-        uint64_t u = 0;
-        for (uint64_t base = a; base < b && u < cap; base += kWave) {
-            const uint64_t i = base + lane;
-            bool first = false;
-            uint32_t v = 0;
-            if (i < b) {
-                v = sorted[i];
-                first = (i == a) || (sorted[i - 1] != v);
+    for (uint64_t i0 = ((uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * kWave;
+         i0 < n_items; i0 += waves * kWave) {
+        const uint32_t ns = (uint32_t)min<uint64_t>(kWave, n_items - i0);
+        const uint64_t i = i0 + lane;
+        const uint64_t first = item_off[i0];
+        const uint64_t excl = (lane < (int)ns ? item_off[i] : item_off[i0 + ns]) - first;
+        const uint64_t a = lane < (int)ns ? item_a[i] : 0u;
+        const uint64_t o = lane < (int)ns ? item_o[i] : 0u;
+        const uint64_t total = item_off[i0 + ns] - first;
+        constexpr int U = 4;
+        for (uint64_t e0 = 0; e0 < total; e0 += (uint64_t)U * kWave) {
+            uint32_t p[U];
+            int64_t po[U];
+            bool ok[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint64_t e = e0 + (uint64_t)u * kWave + lane;
+                // the item of hit e: the last item j < ns whose hits start at or before e
+                int pos = 0;
+#pragma unroll
+                for (int step = kWave / 2; step >= 1; step >>= 1) {
+                    const int cand = pos + step;
+                    const uint64_t ec = __shfl(excl, cand);
+                    if (cand < (int)ns && ec <= e)
+                        pos = cand;
+                }
+                const uint64_t ap = __shfl(a, pos), ep = __shfl(excl, pos);
+                po[u] = (int64_t)__shfl(o, pos);
+                ok[u] = e < total;
+                p[u] = ok[u] ? idx_pos[ap + (e - ep)] : 0u;
             }
-            const uint64_t m = __ballot(first);
-            const uint64_t pos = u + __popcll(m & below);
-            if (EMIT && first && pos < cap)
-                out[out_off[r] + pos] = v;
-            u += __popcll(m);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (ok[u]) {
+                    int64_t z = (int64_t)p[u] - po[u];
+                    if (z < 0)
+                        z = 0;
+                    if ((uint64_t)z > G - 1)
+                        z = (int64_t)(G - 1);
+                    hb[first + e0 + (uint64_t)u * kWave + lane] = (uint32_t)((uint64_t)z / B);
+                }
+            }
         }
-        if (!EMIT && lane == 0)
-            count[r] = u < cap ? u : cap;
+    }
+}
+
+// Wavefront-scope ordering of a wavefront's own LDS traffic between steps.
+__device__ __forceinline__ void seed_wave_fence()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Sorting network for m keys held in x[0 .. m), ascending, P = the power of two
+// >= m: bitonic merges in the form whose comparators all put the smaller key
+// at the lower index (the first step of stage k pairs i with i ^ (k - 1)).
+// Keys at indices >= m act as +infinity and never move down, so comparators
+// that reach past m are skipped and nothing is padded.  Each comparator is
+// handled by one of n_threads threads; `fence` orders the steps.
+template <typename Arr, typename Fence>
+__device__ __forceinline__ void sort_keys(Arr x, uint64_t m, int lane, Fence fence,
+                                          int n_threads = kWave)
+{
+    uint64_t P = 1;
+    while (P < m)
+        P <<= 1;
+    for (uint64_t k = 2; k <= P; k <<= 1) {
+        for (uint64_t j = k >> 1; j >= 1; j >>= 1) {
+            for (uint64_t c = lane; c < P / 2; c += n_threads) {
+                // c-th comparator of the step: lower index lo, partner hi
+                const uint64_t lo = ((c / j) * 2 * j) + (c % j);
+                const uint64_t hi = j == (k >> 1) ? (lo | (k - 1)) - (lo & (k - 1)) : lo + j;
+                const uint64_t a = lo < hi ? lo : hi, b = lo < hi ? hi : lo;
+                if (b < m) {
+                    const uint32_t va = x[a], vb = x[b];
+                    if (vb < va) {
+                        x[a] = vb;
+                        x[b] = va;
+                    }
+                }
+            }
+            fence();
+        }
+    }
+}
+
+// The same network on one key per lane (m <= 64 keys; lanes >= m hold +inf),
+// with the partners exchanged by cross-lane moves; only the stages up to the
+// power of two P >= m run (each block of P lanes is sorted on its own, and the
+// first one holds every key).
+__device__ __forceinline__ uint32_t sort_lanes(uint32_t v, int lane, uint32_t m)
+{
+#pragma unroll
+    for (int k = 2; k <= kWave; k <<= 1) {
+        if ((uint32_t)(k >> 1) >= m)
+            break;
+#pragma unroll
+        for (int j = k >> 1; j >= 1; j >>= 1) {
+            const int partner = j == (k >> 1) ? (lane ^ (k - 1)) : (lane ^ j);
+            const uint32_t w = __shfl(v, partner);
+            v = lane < partner ? min(v, w) : max(v, w);
+        }
+    }
+    return v;
+}
+
+// Distinct keys of the sorted x[0 .. m), at most cap of them, to out[0 ..);
+// returns how many (<= cap).  out may be x itself: writes never pass the
+// position being read, and the last key of a chunk is carried in a register.
+template <typename Src>
+__device__ __forceinline__ uint64_t unique_keys(Src x, uint64_t m, uint32_t cap, uint32_t *out,
+                                                int lane)
+{
+    const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+    uint64_t u = 0;
+    uint32_t carry = 0;
+    for (uint64_t base = 0; base < m && u < cap; base += kWave) {
+        const uint64_t i = base + lane;
+        const uint32_t v = i < m ? x[i] : 0u;
+        const uint32_t prev = __shfl_up(v, 1);
+        const bool first = i < m && (i == 0 || (lane == 0 ? carry : prev) != v);
+        const uint64_t mk = __ballot(first);
+        const uint64_t pos = u + __popcll(mk & below);
+        carry = __shfl(v, kWave - 1);
+        if (first && pos < cap)
+            out[pos] = v;
+        u += __popcll(mk);
+    }
+    return u < cap ? u : cap;
+}
+
+// Per read: its hit bins hb[hit_off[r] ..+ m) reduced to the distinct ones,
+// ascending, up to the cap, written back in place from hit_off[r]; their number
+// to ucnt[r].  seed_sort_kernel takes kSortReads consecutive reads per
+// wavefront (their hit ranges and short lists loaded together): up to 64 hits
+// sorted in registers, up to kMidCap in the wavefront's LDS; longer reads go
+// to a list that seed_sort_long_kernel works through one workgroup per read,
+// sorting kSortCap hits in LDS and longer lists in place in global memory.
+constexpr uint32_t kMidCap = 512;
+constexpr uint32_t kSortCap = 2048;
+constexpr int kSortWaves = 4;
+
+constexpr int kSortReads = 4;  // consecutive reads per wavefront, their loads in flight together
+
+__global__ __launch_bounds__(kSortWaves * kWave) void seed_sort_kernel(
+    const uint64_t *__restrict__ hit_off, uint64_t n_reads, uint32_t cap, uint32_t *__restrict__ hb,
+    uint64_t *__restrict__ ucnt, uint32_t *__restrict__ long_list,
+    uint32_t *__restrict__ long_count)
+{
+    __shared__ uint32_t keys_lds[kSortWaves][kMidCap];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    uint32_t *keys = keys_lds[wv];
+    const uint64_t r0 = ((uint64_t)blockIdx.x * kSortWaves + wv) * kSortReads;
+    if (r0 >= n_reads)
+        return;
+    const int nq = (int)min<uint64_t>(kSortReads, n_reads - r0);
+    // the reads' hit ranges (lanes 0 .. nq), then every short read's hits
+    const uint64_t ho = lane <= nq ? hit_off[r0 + lane] : 0u;
+    uint64_t h[kSortReads + 1];
+#pragma unroll
+    for (int q = 0; q <= kSortReads; ++q)
+        h[q] = __shfl(ho, q);
+    uint32_t v[kSortReads];
+#pragma unroll
+    for (int q = 0; q < kSortReads; ++q) {
+        const uint64_t m = q < nq ? h[q + 1] - h[q] : 0u;
+        v[q] = (m <= (uint64_t)kWave && lane < (int)m) ? hb[h[q] + lane] : 0xffffffffu;
+    }
+#pragma unroll
+    for (int q = 0; q < kSortReads; ++q) {
+        if (q >= nq)
+            break;
+        const uint64_t m = h[q + 1] - h[q];
+        const uint64_t r = r0 + q;
+        uint32_t *hits = hb + h[q];
+        uint64_t u = 0;
+        if (m > kMidCap) {
+            if (lane == 0)
+                long_list[atomicAdd(long_count, 1u)] = (uint32_t)r;
+            continue;
+        } else if (m > (uint64_t)kWave) {
+            for (uint64_t i = lane; i < m; i += kWave)
+                keys[i] = hits[i];
+            seed_wave_fence();
+            sort_keys(keys, m, lane, seed_wave_fence);
+            u = unique_keys(keys, m, cap, hits, lane);
+        } else if (m > 0) {
+            keys[lane] = sort_lanes(v[q], lane, (uint32_t)m);
+            seed_wave_fence();
+            u = unique_keys(keys, m, cap, hits, lane);
+        }
+        seed_wave_fence();  // keys reused by the next read
+        if (lane == 0)
+            ucnt[r] = u;
+    }
+}
+
+__global__ __launch_bounds__(256) void seed_sort_long_kernel(
+    const uint64_t *__restrict__ hit_off, uint32_t cap, uint32_t *__restrict__ hb,
+    uint64_t *__restrict__ ucnt, const uint32_t *__restrict__ long_list,
+    const uint32_t *__restrict__ long_count)
+{
+    __shared__ uint32_t keys[kSortCap];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const uint64_t n = *long_count;
+    for (uint64_t j = blockIdx.x; j < n; j += gridDim.x) {
+        const uint64_t r = long_list[j];
+        const uint64_t h0 = hit_off[r], m = hit_off[r + 1] - h0;
+        uint32_t *hits = hb + h0;
+        if (m <= kSortCap) {
+            for (uint64_t i = t; i < m; i += blockDim.x)
+                keys[i] = hits[i];
+            __syncthreads();
+            sort_keys(keys, m, t, [] { __syncthreads(); }, (int)blockDim.x);
+            if (wv == 0) {
+                const uint64_t u = unique_keys(keys, m, cap, hits, lane);
+                if (lane == 0)
+                    ucnt[r] = u;
+            }
+        } else {
+            // in place in global memory; every step's stores are made visible
+            // to the workgroup's next loads
+            __threadfence();
+            __syncthreads();
+            sort_keys(hits, m, t, [] { __threadfence(); __syncthreads(); }, (int)blockDim.x);
+            if (wv == 0) {
+                const uint64_t u = unique_keys(hits, m, cap, hits, lane);
+                if (lane == 0)
+                    ucnt[r] = u;
+            }
+        }
+        __syncthreads();  // keys reused by the workgroup's next read
+    }
+}
+
+// Groups of 16 lanes, one read per group: its list, list[hit_off[r] ..+
+// ucnt[r]), to the CSR candidates at out[cand_off[r] ..].
+constexpr int kCopyGroup = 16;
+
+__global__ __launch_bounds__(256) void seed_compact_kernel(const uint32_t *__restrict__ list,
+                                                           const uint64_t *__restrict__ hit_off,
+                                                           const uint64_t *__restrict__ cand_off,
+                                                           uint64_t n_reads,
+                                                           uint32_t *__restrict__ out)
+{
+    const int sub = threadIdx.x % kCopyGroup;
+    const uint64_t groups = (uint64_t)gridDim.x * (blockDim.x / kCopyGroup);
+    for (uint64_t r = (uint64_t)blockIdx.x * (blockDim.x / kCopyGroup) + threadIdx.x / kCopyGroup;
+         r < n_reads; r += groups) {
+        const uint64_t src = hit_off[r], dst = cand_off[r], n = cand_off[r + 1] - dst;
+        for (uint64_t i = sub; i < n; i += kCopyGroup)
+            out[dst + i] = list[src + i];
     }
 }
 
@@ -400,15 +651,41 @@ extern "C" void grim_seed_index_free(grim_seed_index_t *si)
         return;
     (void)hipFree(si->d_off);
     (void)hipFree(si->d_pos);
+    for (uint8_t *t : si->tmp)
+        (void)hipFree(t);
     delete si;
 }
 
-extern "C" int grim_seed_candidates(const grim_seed_index_t *si, const grim_batch_t *reads,
+namespace {
+
+// Temporary i of a seed index with at least `bytes` bytes (grown by a quarter
+// more than asked when it has to grow); null when the allocation fails.
+uint8_t *seed_tmp(grim_seed_index *si, int i, uint64_t bytes)
+{
+    if (si->tmp_bytes[i] >= bytes && si->tmp[i])
+        return si->tmp[i];
+    (void)hipFree(si->tmp[i]);
+    si->tmp[i] = nullptr;
+    si->tmp_bytes[i] = 0;
+    const uint64_t want = align_up(bytes + bytes / 4, 256);
+    if (hipMalloc(&si->tmp[i], want) != hipSuccess) {
+        si->tmp[i] = nullptr;
+        return nullptr;
+    }
+    si->tmp_bytes[i] = want;
+    return si->tmp[i];
+}
+
+}  // namespace
+
+extern "C" int grim_seed_candidates(const grim_seed_index_t *csi, const grim_batch_t *reads,
                                     uint64_t bin_stride, uint32_t cap, grim_candidates_t **out,
                                     void *stream)
 {
-    if (!si || !reads || !out || bin_stride == 0 || cap == 0)
+    if (!csi || !reads || !out || bin_stride == 0 || cap == 0)
         return GRIM_E_INVALID;
+    // the index's vectors are not touched; only its cached temporaries change
+    grim_seed_index *si = const_cast<grim_seed_index *>(csi);
     const uint64_t n = reads->n_reads;
     if (n && (!reads->reads_2bit || !reads->read_off || !reads->read_len))
         return GRIM_E_INVALID;
@@ -419,96 +696,135 @@ extern "C" int grim_seed_candidates(const grim_seed_index_t *si, const grim_batc
         return GRIM_E_INVALID;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     int rc = GRIM_OK;
-    uint64_t *hits = nullptr, *hit_off = nullptr, *btmp = nullptr, *ucnt = nullptr;
-    uint32_t *hb = nullptr, *hs = nullptr;
-    void *sort_tmp = nullptr;
-    uint8_t *tmp_reads = nullptr, *tmp_hits = nullptr;  // temporaries, two allocations
-    size_t sort_bytes = 0;
-    uint64_t total_hits = 0, n_pairs = 0;
+    uint32_t *nseeds = nullptr, *long_list = nullptr, *long_count = nullptr;
+    uint64_t *item_base = nullptr, *hit_off = nullptr, *ucnt = nullptr, *btmp = nullptr;
+    uint32_t *item_a = nullptr, *item_cnt = nullptr, *item_o = nullptr, *hb = nullptr;
+    uint64_t *item_off = nullptr, *itmp = nullptr;
+    uint8_t *tmp_reads = nullptr, *tmp_items = nullptr;
+    uint64_t n_items = 0, total_hits = 0, n_pairs = 0;
     grim_candidates *c = new (std::nothrow) grim_candidates();
     if (!c)
         return GRIM_E_NOMEM;
     c->n_reads = n;
+    c->buf = nullptr;
     c->d_off = nullptr;
     c->d_bin = nullptr;
-    const uint64_t nbt = scan_blocks(n) + 1;
+    std::lock_guard<std::mutex> lk(si->mu);
+    const uint64_t nbt = scan_blocks(n + 1) + 1;
+    // fixed item layout: S = max_len / k slots per read, if max_len is given and
+    // n * S stays within 2^26 items
+    const uint32_t S = reads->max_len ? std::max<uint32_t>(1, reads->max_len / si->k) : 0u;
+    const bool fixed = S && n * (uint64_t)S <= (1ull << 26);
     {
-        // per-read temporaries: hit counts, hit offsets, scan block sums, unique counts
-        const uint64_t r8 = align_up((n + 1) * 8, 256), b8 = align_up(nbt * 8, 256);
-        if (hipMalloc(&tmp_reads, 3 * r8 + b8) != hipSuccess ||
-            hipMalloc(&c->d_off, (n + 1) * 8) != hipSuccess) {
+        // per read: seed counts, item bases, hit offsets, list lengths, the
+        // long-read list and its counter, scan block sums
+        const uint64_t r4 = align_up((n + 1) * 4, 256), r8 = align_up((n + 1) * 8, 256);
+        const uint64_t b8 = align_up(nbt * 8, 256);
+        tmp_reads = seed_tmp(si, 0, 2 * r4 + 3 * r8 + 256 + b8);
+        if (!tmp_reads) {
             rc = GRIM_E_NOMEM;
             goto done;
         }
-        hits = reinterpret_cast<uint64_t *>(tmp_reads);
-        hit_off = reinterpret_cast<uint64_t *>(tmp_reads + r8);
-        ucnt = reinterpret_cast<uint64_t *>(tmp_reads + 2 * r8);
-        btmp = reinterpret_cast<uint64_t *>(tmp_reads + 3 * r8);
+        nseeds = reinterpret_cast<uint32_t *>(tmp_reads);
+        long_list = reinterpret_cast<uint32_t *>(tmp_reads + r4);
+        item_base = reinterpret_cast<uint64_t *>(tmp_reads + 2 * r4);
+        hit_off = reinterpret_cast<uint64_t *>(tmp_reads + 2 * r4 + r8);
+        ucnt = reinterpret_cast<uint64_t *>(tmp_reads + 2 * r4 + 2 * r8);
+        long_count = reinterpret_cast<uint32_t *>(tmp_reads + 2 * r4 + 3 * r8);
+        btmp = reinterpret_cast<uint64_t *>(tmp_reads + 2 * r4 + 3 * r8 + 256);
     }
-    if (n) {
-        hipLaunchKernelGGL(seed_count_kernel, dim3(grid_for(n, dev)), dim3(256), 0, s,
-                           reads->reads_2bit, reads->n_read_words, reads->read_off, reads->read_len,
-                           n, si->k, si->d_off, hits);
+    // the (read, seed) items: a fixed number S = max_len / k of slots per read
+    // when that stays small, else exactly each read's seeds (counted and scanned)
+    if (fixed) {
+        n_items = n * S;
+    } else {
+        if (n) {
+            hipLaunchKernelGGL(seed_nseeds_kernel, dim3(grid_for(n, dev)), dim3(256), 0, s,
+                               reads->read_off, reads->read_len, n, reads->n_read_words, si->k,
+                               reads->max_len, nseeds);
+            SEED_TRY(hipGetLastError());
+        }
+        SEED_TRY(scan_u64(s, nseeds, true, n, item_base, btmp, btmp + nbt - 1));
+        SEED_TRY(hipMemcpyAsync(&n_items, item_base + n, 8, hipMemcpyDeviceToHost, s));
+        SEED_TRY(hipStreamSynchronize(s));
+    }
+    {
+        const uint64_t i4 = align_up((n_items + 1) * 4, 256), i8 = align_up((n_items + 1) * 8, 256);
+        const uint64_t ib = align_up((scan_blocks(n_items) + 1) * 8, 256);
+        tmp_items = seed_tmp(si, 1, 3 * i4 + i8 + ib);
+        if (!tmp_items) {
+            rc = GRIM_E_NOMEM;
+            goto done;
+        }
+        item_a = reinterpret_cast<uint32_t *>(tmp_items);
+        item_cnt = reinterpret_cast<uint32_t *>(tmp_items + i4);
+        item_o = reinterpret_cast<uint32_t *>(tmp_items + 2 * i4);
+        item_off = reinterpret_cast<uint64_t *>(tmp_items + 3 * i4);
+        itmp = reinterpret_cast<uint64_t *>(tmp_items + 3 * i4 + i8);
+    }
+    if (fixed && n_items) {
+        hipLaunchKernelGGL(seed_items_fixed_kernel, dim3(grid_for(n_items, dev)), dim3(256), 0, s,
+                           reads->reads_2bit, reads->n_read_words, reads->read_off,
+                           reads->read_len, n_items, S, reads->max_len, si->k, si->d_off, item_a,
+                           item_cnt, item_o);
+        SEED_TRY(hipGetLastError());
+    } else if (!fixed && n) {
+        hipLaunchKernelGGL(seed_items_kernel, dim3(grid_for(n, dev)), dim3(256), 0, s,
+                           reads->reads_2bit, reads->n_read_words, reads->read_off, item_base, n,
+                           si->k, si->d_off, item_a, item_cnt, item_o);
         SEED_TRY(hipGetLastError());
     }
-    SEED_TRY(scan_u64(s, hits, false, n, hit_off, btmp, btmp + nbt - 1));
-    SEED_TRY(hipMemcpyAsync(&total_hits, hit_off + n, 8, hipMemcpyDeviceToHost, s));
+    SEED_TRY(scan_u64(s, item_cnt, true, n_items, item_off, itmp,
+                      itmp + scan_blocks(n_items)));
+    hipLaunchKernelGGL(seed_hit_off_kernel, dim3(grid_for(n + 1, dev)), dim3(256), 0, s,
+                       fixed ? nullptr : item_base, (uint64_t)S, item_off, n, hit_off, long_count);
+    SEED_TRY(hipGetLastError());
+    SEED_TRY(hipMemcpyAsync(&total_hits, item_off + n_items, 8, hipMemcpyDeviceToHost, s));
     SEED_TRY(hipStreamSynchronize(s));
     if (total_hits >= 0x7fffffffull) {
         rc = GRIM_E_UNSUPPORTED;
         goto done;
     }
-    if (n) {
-        // per-hit temporaries: hit bins, sorted hit bins, the sort's own storage
-        SEED_TRY(hipcub::DeviceSegmentedRadixSort::SortKeys(
-            nullptr, sort_bytes, static_cast<const uint32_t *>(nullptr),
-            static_cast<uint32_t *>(nullptr), (int)total_hits, (int)n, hit_off, hit_off + 1, 0, 32,
-            s));
-    }
-    {
-        const uint64_t h4 = align_up((total_hits + 1) * 4, 256);
-        if (hipMalloc(&tmp_hits, 2 * h4 + align_up(sort_bytes ? sort_bytes : 1, 256)) !=
-            hipSuccess) {
-            rc = GRIM_E_NOMEM;
-            goto done;
-        }
-        hb = reinterpret_cast<uint32_t *>(tmp_hits);
-        hs = reinterpret_cast<uint32_t *>(tmp_hits + h4);
-        sort_tmp = tmp_hits + 2 * h4;
-    }
-    if (n) {
-        hipLaunchKernelGGL(seed_emit_kernel, dim3(grid_for(n * 64, dev)), dim3(256), 0, s,
-                           reads->reads_2bit, reads->n_read_words, reads->read_off,
-                           reads->read_len, n, si->k, si->d_off, si->d_pos, si->G, bin_stride,
-                           hit_off, hb);
-        SEED_TRY(hipGetLastError());
-        SEED_TRY(hipcub::DeviceSegmentedRadixSort::SortKeys(sort_tmp, sort_bytes, hb, hs,
-                                                            (int)total_hits, (int)n, hit_off,
-                                                            hit_off + 1, 0, 32, s));
-        hipLaunchKernelGGL(unique_kernel<false>, dim3(grid_for(n * 64, dev)), dim3(256), 0, s, hs,
-                           hit_off, n, cap, ucnt, nullptr, nullptr);
-        SEED_TRY(hipGetLastError());
-    }
-    SEED_TRY(scan_u64(s, ucnt, false, n, c->d_off, btmp, btmp + nbt - 1));
-    SEED_TRY(hipMemcpyAsync(&n_pairs, c->d_off + n, 8, hipMemcpyDeviceToHost, s));
-    SEED_TRY(hipStreamSynchronize(s));
-    if (hipMalloc(&c->d_bin, (n_pairs + 1) * 4) != hipSuccess) {
+    // every hit's bin, then the per-read lists in place; the result (offsets
+    // and bins in one allocation) is no longer than the hits together
+    hb = reinterpret_cast<uint32_t *>(seed_tmp(si, 2, (total_hits + 1) * 4));
+    if (!hb || hipMalloc(&c->buf, align_up((n + 1) * 8, 256) + (total_hits + 1) * 4) !=
+                   hipSuccess) {
+        c->buf = nullptr;
         rc = GRIM_E_NOMEM;
         goto done;
     }
+    c->d_off = reinterpret_cast<uint64_t *>(c->buf);
+    c->d_bin = reinterpret_cast<uint32_t *>(c->buf + align_up((n + 1) * 8, 256));
     if (n) {
-        hipLaunchKernelGGL(unique_kernel<true>, dim3(grid_for(n * 64, dev)), dim3(256), 0, s, hs,
-                           hit_off, n, cap, nullptr, c->d_off, c->d_bin);
+        if (n_items) {
+            hipLaunchKernelGGL(seed_emit_kernel, dim3(grid_for(n_items, dev)), dim3(256), 0, s,
+                               item_a, item_o, item_off, n_items, si->d_pos, si->G, bin_stride, hb);
+            SEED_TRY(hipGetLastError());
+        }
+        const uint64_t per_block = (uint64_t)kSortWaves * kSortReads;
+        hipLaunchKernelGGL(seed_sort_kernel, dim3((uint32_t)((n + per_block - 1) / per_block)),
+                           dim3(kSortWaves * kWave), 0, s, hit_off, n, cap, hb, ucnt, long_list,
+                           long_count);
         SEED_TRY(hipGetLastError());
     }
+    if (n) {
+        hipLaunchKernelGGL(seed_sort_long_kernel, dim3(grid_for((uint64_t)256 * 8 * 256, dev)),
+                           dim3(256), 0, s, hit_off, cap, hb, ucnt, long_list, long_count);
+        SEED_TRY(hipGetLastError());
+    }
+    SEED_TRY(scan_u64(s, ucnt, false, n, c->d_off, btmp, btmp + nbt - 1));
+    if (n) {
+        hipLaunchKernelGGL(seed_compact_kernel, dim3(grid_for(n * kCopyGroup, dev)), dim3(256), 0,
+                           s, hb, hit_off, c->d_off, n, c->d_bin);
+        SEED_TRY(hipGetLastError());
+    }
+    SEED_TRY(hipMemcpyAsync(&n_pairs, c->d_off + n, 8, hipMemcpyDeviceToHost, s));
     SEED_TRY(hipStreamSynchronize(s));
     c->n_pairs = n_pairs;
 done:
-    (void)hipFree(tmp_reads);
-    (void)hipFree(tmp_hits);
     if (rc != GRIM_OK) {
-        (void)hipFree(c->d_off);
-        (void)hipFree(c->d_bin);
+        (void)hipFree(c->buf);
         delete c;
         return rc;
     }
@@ -550,7 +866,6 @@ extern "C" void grim_candidates_free(grim_candidates_t *c)
 {
     if (!c)
         return;
-    (void)hipFree(c->d_off);
-    (void)hipFree(c->d_bin);
+    (void)hipFree(c->buf);
     delete c;
 }

@@ -310,6 +310,7 @@ struct grim_server {
     uint64_t reqs_in_ticks = 0, peak_bytes = 0;
     std::vector<double> lat;
     double busy_s = 0;
+    double launch_s = 0, retire_s = 0;  // scheduler thread time in launch_tick / retire
     int running_ticks = 0;
     Clock::time_point busy_since;
 
@@ -796,13 +797,22 @@ void grim_server::run()
             seen = bell;  // a ring after this point wakes the wait below
         }
         for (auto &s : slots)
-            if (s->busy && s->finished.load(std::memory_order_acquire))
+            if (s->busy && s->finished.load(std::memory_order_acquire)) {
+                const auto t0 = Clock::now();
                 retire(*s);
+                retire_s += std::chrono::duration<double>(Clock::now() - t0).count();
+            }
         if (stop && running_ticks == 0)
             break;
-        if (!stop)
-            while (launch_tick(lk)) {
+        if (!stop) {
+            for (;;) {
+                const auto t0 = Clock::now();
+                const bool launched = launch_tick(lk);
+                if (!launched)
+                    break;
+                launch_s += std::chrono::duration<double>(Clock::now() - t0).count();
             }
+        }
         lk.unlock();
         {
             // a bounded sleep as well, measured on the system clock: its timed
@@ -1173,12 +1183,15 @@ extern "C" int grim_serve_stats(grim_server_t *s, grim_serve_stats_t *out, int r
     out->pairs_per_s = busy > 0 ? s->pairs_done / busy : 0.0;
     out->peak_device_bytes = s->peak_bytes;
     out->mean_requests_per_tick = s->ticks ? (double)s->reqs_in_ticks / s->ticks : 0.0;
+    out->sched_launch_s = s->launch_s;
+    out->sched_retire_s = s->retire_s;
     if (reset) {
         s->submitted = s->completed = s->cancelled = s->failed = s->ticks = s->pairs_done = 0;
         s->reqs_in_ticks = 0;
         s->peak_bytes = s->pool->used();
         s->lat.clear();
         s->busy_s = 0;
+        s->launch_s = s->retire_s = 0;
         if (s->running_ticks > 0)
             s->busy_since = Clock::now();
     }
