@@ -127,14 +127,17 @@ def cpu_baseline_leg(w, counts, bits, n_threads, cpu_pairs=0):
     return cpu, parity
 
 
-def link_probe(torch, n_bytes=256 << 20, reps=5):
+def link_probe(torch, n_bytes=256 << 20, reps=5, pairs=4):
     """Host link rates (GB/s) with page-locked buffers: one direction at a
-    time, then both at once on two streams (best of reps)."""
+    time, then both at once on two streams (best of reps).  Copies on two
+    streams do not always run on different copy engines (then the two
+    directions take turns at the one-way rate), so both-at-once is tried on
+    `pairs` freshly created stream pairs and the best is kept, with every
+    pair's rate listed."""
     h = torch.empty(n_bytes, dtype=torch.uint8, pin_memory=True)
     h2 = torch.empty(n_bytes, dtype=torch.uint8, pin_memory=True)
     d = torch.empty(n_bytes, dtype=torch.uint8, device="cuda")
     d2 = torch.empty(n_bytes, dtype=torch.uint8, device="cuda")
-    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
 
     def best(fn):
         fn()
@@ -147,20 +150,27 @@ def link_probe(torch, n_bytes=256 << 20, reps=5):
             t.append(time.perf_counter() - t0)
         return n_bytes / min(t) / 1e9
 
-    def up():
-        with torch.cuda.stream(s1):
+    s1 = torch.cuda.Stream()
+
+    def up(s=s1):
+        with torch.cuda.stream(s):
             d.copy_(h, non_blocking=True)
 
-    def down():
-        with torch.cuda.stream(s1):
+    def down(s=s1):
+        with torch.cuda.stream(s):
             h.copy_(d, non_blocking=True)
 
-    def both():
-        up()
-        with torch.cuda.stream(s2):
-            h2.copy_(d2, non_blocking=True)
+    both = []
+    for _ in range(pairs):
+        a, b = torch.cuda.Stream(), torch.cuda.Stream()
 
-    out = dict(h2d_gbs=best(up), d2h_gbs=best(down), both_each_gbs=best(both))
+        def fn(a=a, b=b):
+            up(a)
+            with torch.cuda.stream(b):
+                h2.copy_(d2, non_blocking=True)
+        both.append(best(fn))
+    out = dict(h2d_gbs=best(up), d2h_gbs=best(down), both_each_gbs=max(both),
+               both_each_gbs_per_stream_pair=both)
     del h, h2, d, d2
     return out
 
@@ -210,21 +220,25 @@ def serving_leg(g, idx, w, rng, loads=(0.25, 0.5, 0.75, 0.9), n_requests=10_000,
         for t in tickets:
             finish(srv.wait(t)[0], t)
 
-    # warm-up over the whole pool (first use of every buffer; the server's
-    # staging buffers reach their final size), then closed-loop capacity: the
-    # whole pool submitted at once, twice (each buffer is in flight at most once
-    # at a time), pairs over the mean wall time
+    # warm-up over the whole pool (first use of every buffer), then closed-loop
+    # capacity: the whole pool submitted at once (each buffer is in flight at
+    # most once at a time), six times; pairs over the median wall time
     drain([submit(hb) for hb in reqs])
     srv.stats(reset=True)
     walls = []
-    for _ in range(2):
+    for _ in range(6):
         t0 = time.perf_counter()
         drain([submit(hb) for hb in reqs])
         walls.append(time.perf_counter() - t0)
-    capacity = sum(hb.n_pairs for hb in reqs) / float(np.mean(walls))
+    capacity = sum(hb.n_pairs for hb in reqs) / float(np.median(walls))
     cap_stats = srv.stats(reset=True)
-    # scheduler thread time during the two bursts, against their wall time
-    sched_busy = (cap_stats["sched_launch_s"] + cap_stats["sched_retire_s"]) / max(1e-9, sum(walls))
+    # host thread time during the bursts, against their wall time: the
+    # workers' mean occupancy (staging, queuing, retiring) and the admission
+    # thread's
+    workers = n_streams * (2 if bits_only else 1)  # the server's default ticks per stream
+    worker_busy = (cap_stats["sched_launch_s"] + cap_stats["sched_retire_s"]) / \
+        max(1e-9, workers * sum(walls))
+    admit_busy = cap_stats["sched_admit_s"] / max(1e-9, sum(walls))
     checked = None
     if expect is not None and inplace and not bits_only:
         # every pool request's results, as the capacity bursts left them, against
@@ -257,7 +271,8 @@ def serving_leg(g, idx, w, rng, loads=(0.25, 0.5, 0.75, 0.9), n_requests=10_000,
                capacity_burst_s=walls,
                capacity_pairs_per_s=capacity,
                capacity_ticks=cap_stats["ticks"],
-               capacity_scheduler_busy=sched_busy,
+               capacity_worker_busy=worker_busy,
+               capacity_admission_busy=admit_busy,
                results_checked=checked,
                link_bytes_per_pair=dict(up=up_bytes / n_pairs_all, down=down_bytes / n_pairs_all),
                points=[])
@@ -303,6 +318,7 @@ def serving_leg(g, idx, w, rng, loads=(0.25, 0.5, 0.75, 0.9), n_requests=10_000,
                                   mean_requests_per_tick=st["mean_requests_per_tick"],
                                   sched_launch_s=st["sched_launch_s"],
                                   sched_retire_s=st["sched_retire_s"],
+                                  sched_admit_s=st["sched_admit_s"],
                                   ticks=st["ticks"],
                                   arrivals_delayed_by_full_pool=late))
     srv.destroy()

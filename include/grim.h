@@ -386,17 +386,23 @@ void grim_graph_destroy(grim_graph_t *g);
 
 /* ------------------------------------------------------------------ serving */
 /* A continuous-batching server over one resident index.  Requests (host
- * batches) are copied at submit time; a scheduler thread admits queued
- * requests while their device bytes fit in the HBM budget and a slot is free,
- * fuses the admitted requests of one tick into a single batched launch on one
- * of n_streams streams, and keeps admitting new requests while earlier ticks
- * run.  A request with more pairs than max_tick_pairs is cut at read
- * boundaries into parts that run as separate ticks, so that its copies and
- * launches overlap across streams.  Results are bit-identical to filtering
- * each request alone.  Mirrors the
- * overlap of filtering with the mapper's alignment through a bitmask buffer
- * (Sections "Mapping GRIM-Filter to 3D-Stacked Memory with PIM" and "GRIM-Filter
- * Parallelization"). */
+ * batches) are copied at submit time (or used in place); an admission thread
+ * admits queued requests while their device bytes fit in the HBM budget and a
+ * slot is free, fuses the admitted requests of one tick into a single batched
+ * launch, and keeps admitting new requests while earlier ticks run.  Up to
+ * n_streams x ticks_per_stream ticks are in flight, each in a slot with a
+ * worker thread that stages it, queues its copies, filter and result copies on
+ * the slot's stream and retires it; ticks on different streams overlap on the
+ * device, and a stream's next tick waits queued behind its current one.  When
+ * results include counts, ticks take turns to queue their input copies (a turn
+ * ends when the tick's inputs are on the device), so that uploads run one at a
+ * time and the ticks' downloads are staggered against them.  A
+ * request with more pairs than max_tick_pairs is cut at read boundaries into
+ * parts that run as separate ticks, so that its copies and launches overlap
+ * across streams.  Results are bit-identical to filtering each request alone.
+ * Mirrors the overlap of filtering with the mapper's alignment through a
+ * bitmask buffer (Sections "Mapping GRIM-Filter to 3D-Stacked Memory with PIM"
+ * and "GRIM-Filter Parallelization"). */
 typedef struct grim_server grim_server_t;
 
 /* Server option: a request's results are its pass bits alone (the seed
@@ -417,6 +423,9 @@ typedef struct grim_serve_cfg {
                                    of whole reads (0 = 8M)                          */
     uint32_t max_len;           /* longest read accepted (0 = 1024)                 */
     uint32_t flags;             /* GRIM_SERVE_* options (0: counts and pass bits)   */
+    uint32_t ticks_per_stream;  /* ticks queued on one stream at once: the next one
+                                   waits behind the current one (0 = 1, or 2 with
+                                   GRIM_SERVE_PASS_BITS_ONLY; at most 4)            */
 } grim_serve_cfg_t;
 
 typedef struct grim_req_stats {
@@ -437,8 +446,10 @@ typedef struct grim_serve_stats {
     double pairs_per_s;       /* pairs_done / busy_s                                */
     uint64_t peak_device_bytes;
     double mean_requests_per_tick;
-    double sched_launch_s;    /* scheduler thread time spent staging and queueing ticks */
-    double sched_retire_s;    /* scheduler thread time spent handing results back       */
+    double sched_launch_s;    /* worker time staging and queueing ticks (all workers,
+                                 waits for upload turns excluded)                     */
+    double sched_retire_s;    /* worker time handing results back (all workers)         */
+    double sched_admit_s;     /* admission thread time forming ticks                    */
 } grim_serve_stats_t;
 
 /* Create a server on the current device.  It allocates its device pool

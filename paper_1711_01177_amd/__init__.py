@@ -90,7 +90,8 @@ class grim_tuning_t(ctypes.Structure):
 
 class grim_serve_cfg_t(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", _u64), ("max_inflight", _u32), ("n_streams", _u32),
-                ("max_tick_pairs", _u32), ("max_len", _u32), ("flags", _u32)]
+                ("max_tick_pairs", _u32), ("max_len", _u32), ("flags", _u32),
+                ("ticks_per_stream", _u32)]
 
 
 class grim_req_stats_t(ctypes.Structure):
@@ -105,7 +106,7 @@ class grim_serve_stats_t(ctypes.Structure):
                 ("max_ms", ctypes.c_double), ("busy_s", ctypes.c_double),
                 ("pairs_per_s", ctypes.c_double), ("peak_device_bytes", _u64),
                 ("mean_requests_per_tick", ctypes.c_double), ("sched_launch_s", ctypes.c_double),
-                ("sched_retire_s", ctypes.c_double)]
+                ("sched_retire_s", ctypes.c_double), ("sched_admit_s", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -705,12 +706,13 @@ class Server:
     """Continuous-batching server over a resident index (owns a grim_server_t)."""
 
     def __init__(self, index, hbm_budget_bytes=0, max_inflight=0, n_streams=0, max_tick_pairs=0,
-                 max_len=0, pass_bits_only=False):
+                 max_len=0, pass_bits_only=False, ticks_per_stream=0):
         self.index = index
         self.pass_bits_only = bool(pass_bits_only)
         cfg = grim_serve_cfg_t(int(hbm_budget_bytes), int(max_inflight), int(n_streams),
                                int(max_tick_pairs), int(max_len),
-                               GRIM_SERVE_PASS_BITS_ONLY if pass_bits_only else 0)
+                               GRIM_SERVE_PASS_BITS_ONLY if pass_bits_only else 0,
+                               int(ticks_per_stream))
         self._h = ctypes.c_void_p()
         _check(_lib.grim_serve_create(index.handle, ctypes.byref(cfg), ctypes.byref(self._h)),
                "grim_serve_create")

@@ -3,23 +3,44 @@
 // Requests are host batches (reads + candidate locations).  At submit the
 // request's arrays are copied once, into a block of a pinned host arena
 // allocated when the server is created (pageable memory only when the arena is
-// full), with room for its results.  A scheduler thread repeatedly
-//   (1) retires finished ticks: realigns each request's slice of the fused pass
-//       bits, and marks the requests done;
-//   (2) while a stream slot is free, admits queued requests in arrival order
-//       while their device bytes fit in what is left of the HBM budget and the
-//       tick has fewer than max_tick_pairs pairs, fuses them into one batch and
-//       queues on that slot's stream: H2D copies (large array slices straight
-//       from the request's pinned block, runs of small slices through the
-//       slot's staging buffer, re-based offset arrays always staged), one
-//       batched filter launch, and D2H copies (large count slices straight into
-//       the request's result area).
+// full), with room for its results; in-place submission uses the caller's
+// pinned arrays directly.
+//
+// Threads.  One admission thread and one worker per slot; each of the
+// n_streams streams carries the ticks of ticks_per_stream slots.
+//   - The admission thread, while a slot is free, admits queued requests in
+//     arrival order while their device bytes fit in what is left of the HBM
+//     budget and the tick has fewer than max_tick_pairs pairs, reserves the
+//     tick's device memory, and hands the tick to the slot's worker.
+//   - The slot's worker stages the tick and queues it on the slot's stream:
+//     H2D copies (large array slices straight from the request's pinned
+//     memory, small slices packed through the slot's staging buffer, re-based
+//     per-read arrays always staged), the batched filter, D2H copies (large
+//     count slices straight into the request's result area) and a completion
+//     notice.  When the notice arrives it retires the tick: copies the small
+//     count slices and realigns each request's slice of the fused pass bits,
+//     then closes the parts, frees the device memory and rings the admission
+//     thread.
+// Staging and retirement of different ticks run on different host threads.
+// Ticks on different streams overlap on the device: one tick's inputs go up
+// while another's results come down.  Two policies keep the host link busy, one
+// per kind of result (both chosen by measurement on the full-size workload):
+//   - counts and pass bits (both directions of the link loaded): upload turns.
+//     A tick queues its input copies only when the tick before it at the gate
+//     has its inputs on the device (a notice queued behind them ends the turn),
+//     so uploads run one at a time at the link's full rate and the ticks reach
+//     their filters and result copies staggered, instead of all streams moving
+//     their data in the same direction at once;
+//   - pass bits only (the upload direction alone loaded): no turns, and two
+//     slots per stream by default, so that a stream's next tick is queued
+//     behind its current one while the host retires the tick before.
+//
 // A request with more pairs than a tick has room for is admitted in parts, cut
 // at read boundaries; its parts run as separate ticks on the free streams, so
 // one part's H2D copy overlaps another part's filter and D2H copy, and the
-// request is done when its last part has been retired.  Ticks on different
-// streams overlap on the device, and requests that arrive while ticks run join
-// the next tick as soon as memory and a slot free up.
+// request is done when its last part has been retired.  Two parts of one
+// request can share a pass-bit word at their boundary; workers merge such
+// words with an atomic OR and store the words wholly inside a part.
 //
 // Fusing and splitting only concatenate, cut and re-base offsets, and every
 // pair is computed by the same kernel from the same read and bin, so each
@@ -27,10 +48,10 @@
 //
 // The scheduler makes no HIP call itself: device memory, streams, copies, the
 // filter launch and completion notices go through grim_serve::backend()
-// (grim_serve_backend.h).  A tick's completion is signalled by a host function
-// queued on its stream after its last copy; it marks the slot finished and
-// rings the scheduler's doorbell, which is the only thing the scheduler waits
-// on (submissions and shutdown ring it too), so nothing polls.
+// (grim_serve_backend.h).  A tick's completion notice is a host function
+// queued on its stream after its last copy; it wakes the slot's worker.
+// Submissions, retired ticks and shutdown ring the admission thread's
+// doorbell, the only thing it waits on, so nothing polls.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -214,12 +235,16 @@ struct Request {
 };
 
 // Byte layout of one fused tick on the device (and in the staging buffer).
+// The per-read arrays come first (always staged: one copy), then the packed
+// words and the bin ids; the outputs are counts, pass bits and the filter's
+// workspace, whose first word is the launch's status word, so that the pass
+// bits and the status come back in one copy.
 struct Layout {
-    uint64_t words, read_off, read_len, read_e, cand_off, cand_bin;  // inputs
-    uint64_t in_bytes;
-    uint64_t counts, bits, status, out_bytes;  // outputs, relative to `out_base`
+    uint64_t read_off, cand_off, read_len, read_e, meta_bytes;  // per-read arrays
+    uint64_t words, cand_bin, in_bytes;                         // inputs
     uint64_t out_base;
-    uint64_t ws, ws_bytes;
+    uint64_t counts, bits, ws, out_bytes;  // outputs, relative to `out_base`
+    uint64_t ws_bytes;
     uint64_t total;
 };
 
@@ -227,29 +252,27 @@ Layout plan(uint64_t n_words, uint64_t n_reads, uint64_t n_pairs, uint64_t ws_by
 {
     Layout L;
     uint64_t o = 0;
-    L.words = o;
-    o = align256(o + n_words * 4);
     L.read_off = o;
     o = align256(o + n_reads * 8);
+    L.cand_off = o;
+    o = align256(o + (n_reads + 1) * 8);
     L.read_len = o;
     o = align256(o + n_reads * 4);
     L.read_e = o;
     o = align256(o + n_reads * 4);
-    L.cand_off = o;
-    o = align256(o + (n_reads + 1) * 8);
+    L.meta_bytes = o;
+    L.words = o;
+    o = align256(o + n_words * 4);
     L.cand_bin = o;
     o = align256(o + n_pairs * 4);
     L.in_bytes = o;
     L.out_base = o;
     L.counts = 0;
     L.bits = align256(n_pairs * 4);
-    L.status = L.bits + align256(((n_pairs + 31) / 32) * 4 + 4);
-    L.out_bytes = L.status + 256;
-    o += L.out_bytes;
-    L.ws = o;
+    L.ws = L.bits + align256(((n_pairs + 31) / 32) * 4 + 4);
     L.ws_bytes = align256(ws_bytes);
-    o += L.ws_bytes;
-    L.total = o;
+    L.out_bytes = L.ws + L.ws_bytes;
+    L.total = o + L.out_bytes;
     return L;
 }
 
@@ -262,17 +285,36 @@ struct Part {
     bool counts_direct = false;    // counts came back by direct DMA
 };
 
+// One host <-> device copy of a tick.
+struct CopyOp {
+    void *dst;
+    const void *src;
+    uint64_t bytes;
+};
+
 struct Slot {
     grim_server *srv = nullptr;
-    void *stream = nullptr;
+    void *stream = nullptr;        // shared with ticks_per_stream - 1 other slots
     uint8_t *stage = nullptr;      // pinned staging buffer, mirrors the tick layout
     uint64_t stage_bytes = 0;
+    // guarded by the server lock; the tick fields below are written by the
+    // admission thread while busy is false and belong to the worker from the
+    // hand-off until it clears busy
     bool busy = false;
-    std::atomic<bool> finished{false};  // set by the tick's completion notice
     std::vector<Part> parts;
     Layout lay;
     uint64_t dev_off = 0;
     uint64_t tick = 0;
+    uint32_t e_den = 0;
+    double turn_wait_s = 0;        // the last launch's wait for its upload turn
+    // hand-off between the admission thread, the completion notice and the
+    // worker (m is never held while taking the server lock or calling the backend)
+    std::mutex m;
+    std::condition_variable cv;
+    bool job = false;              // a tick has been handed over
+    bool notice = false;           // the tick's completion notice has run
+    bool quit = false;
+    std::thread worker;
 };
 
 }  // namespace
@@ -289,6 +331,15 @@ struct grim_server {
     std::mutex arena_mu;
     std::vector<std::unique_ptr<Slot>> slots;
     uint64_t stage_bytes = 0;          // each slot's staging buffer: the largest tick layout
+    std::vector<void *> streams;       // slot i queues its ticks on streams[i % n_streams]
+    // upload turns (taken when results include counts): ticks queue their
+    // input copies one at a time, in the order they reach the gate; a turn ends
+    // when the tick's inputs are on the device
+    bool upload_turns = false;
+    std::mutex up_mu;
+    std::condition_variable up_cv;
+    uint64_t up_next = 0, up_turn = 0;
+    void upload_turn_end();
 
     std::mutex mu;
     std::condition_variable cv_done;
@@ -310,18 +361,32 @@ struct grim_server {
     uint64_t reqs_in_ticks = 0, peak_bytes = 0;
     std::vector<double> lat;
     double busy_s = 0;
-    double launch_s = 0, retire_s = 0;  // scheduler thread time in launch_tick / retire
+    double admit_s = 0;                 // admission thread time forming ticks
+    double launch_s = 0, retire_s = 0;  // worker time staging + queuing / retiring, summed
     int running_ticks = 0;
     Clock::time_point busy_since;
 
     void run();
     void ring();
-    bool launch_tick(std::unique_lock<std::mutex> &lk);
-    void retire(Slot &s);
+    bool admit_tick();
+    void work(Slot &s);
+    int launch(Slot &s);
+    void retire(Slot &s, double t_launch);
+    void close_tick(Slot &s, int rc, const std::vector<uint32_t> &part_flags, double t_launch,
+                    double t_retire);
     void part_closed(Request &r, Clock::time_point now);
     void drop_from_queue(const Request &r);
     void free_block(Request &r);
 };
+
+void grim_server::upload_turn_end()
+{
+    {
+        std::lock_guard<std::mutex> lk(up_mu);
+        ++up_turn;
+    }
+    up_cv.notify_all();
+}
 
 void grim_server::ring()
 {
@@ -334,13 +399,22 @@ void grim_server::ring()
 
 namespace {
 
+// Notice queued behind a tick's input copies: the next tick's turn to upload.
+void on_upload_done(void *arg)
+{
+    static_cast<Slot *>(arg)->srv->upload_turn_end();
+}
+
 // Completion notice of a tick (runs on a backend thread once the tick's last
-// copy has completed): mark the slot and wake the scheduler.
+// copy has completed): wake the slot's worker.
 void on_tick_done(void *arg)
 {
     Slot *slot = static_cast<Slot *>(arg);
-    slot->finished.store(true, std::memory_order_release);
-    slot->srv->ring();
+    {
+        std::lock_guard<std::mutex> lk(slot->m);
+        slot->notice = true;
+    }
+    slot->cv.notify_one();
 }
 
 }  // namespace
@@ -369,26 +443,54 @@ void grim_server::free_block(Request &r)
 
 namespace {
 
-// OR n bits of src starting at bit sb into dst starting at bit db (dst words
-// outside [db, db + n) keep their other bits).  src must be readable one word
-// past its last used bit.
-void or_bits(uint32_t *dst, uint64_t db, const uint32_t *src, uint64_t sb, uint64_t n)
+// Bits [bit, bit + 32) of src as one word (src readable one word past them).
+inline uint32_t word_at(const uint32_t *src, uint64_t bit)
 {
-    uint64_t done = 0;
-    while (done < n) {
-        const uint64_t d = db + done, sp = sb + done;
-        const uint32_t dsh = (uint32_t)(d & 31);
-        const uint64_t take = std::min<uint64_t>(32 - dsh, n - done);
-        const uint32_t ssh = (uint32_t)(sp & 31);
-        uint32_t x = src[sp >> 5] >> ssh;
-        if (ssh && ssh + take > 32)
-            x |= src[(sp >> 5) + 1] << (32 - ssh);
+    const uint64_t w = bit >> 5;
+    const uint32_t sh = (uint32_t)(bit & 31);
+    return sh ? (src[w] >> sh) | (src[w + 1] << (32 - sh)) : src[w];
+}
+
+// Writes bits [sb, sb + n) of src to bits [db, db + n) of dst.  The bits of dst
+// in that range are zero and belong to this call alone, but the first and last
+// word may hold bits of a neighbouring part of the same request that another
+// worker writes at the same time: those words are merged with an atomic OR, the
+// words wholly inside the range are stored.  src must be readable one word past
+// its last used bit.
+void put_bits(uint32_t *dst, uint64_t db, const uint32_t *src, uint64_t sb, uint64_t n)
+{
+    const uint64_t end = db + n;
+    auto merge = [&](uint64_t d, uint64_t take) {  // `take` bits at d, in one word of dst
+        uint32_t x = word_at(src, sb + (d - db));
         if (take < 32)
             x &= (1u << take) - 1u;
-        dst[d >> 5] |= x << dsh;
-        done += take;
+        __atomic_fetch_or(&dst[d >> 5], x << (d & 31), __ATOMIC_RELAXED);
+    };
+    uint64_t d = db;
+    if (n && (d & 31)) {
+        const uint64_t take = std::min<uint64_t>(32 - (d & 31), n);
+        merge(d, take);
+        d += take;
     }
+    const uint64_t whole_end = end & ~31ull;
+    if (d < whole_end) {
+        const uint64_t s0 = sb + (d - db);
+        const uint64_t k0 = d >> 5, k1 = whole_end >> 5;
+        const uint32_t sh = (uint32_t)(s0 & 31);
+        const uint32_t *sp = src + (s0 >> 5);
+        if (sh == 0) {
+            std::memcpy(dst + k0, sp, (k1 - k0) * 4);
+        } else {
+            for (uint64_t k = k0; k < k1; ++k, ++sp)
+                dst[k] = (sp[0] >> sh) | (sp[1] << (32 - sh));
+        }
+        d = whole_end;
+    }
+    if (d < end)
+        merge(d, end - d);
 }
+
+double secs(Clock::duration d) { return std::chrono::duration<double>(d).count(); }
 
 }  // namespace
 
@@ -428,14 +530,55 @@ void grim_server::drop_from_queue(const Request &r)
         }
 }
 
-void grim_server::retire(Slot &s)
+// Ends s's tick under the server lock (worker thread): with rc != GRIM_OK
+// every part's request fails and the reads of it still queued are dropped;
+// otherwise each part's flags go to its request.  Then the parts are closed,
+// the tick's device memory is released, the slot is freed and the admission
+// thread is rung.
+void grim_server::close_tick(Slot &s, int rc, const std::vector<uint32_t> &part_flags,
+                             double t_launch, double t_retire)
 {
-    // called with mu held, after s.done completed
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        const auto now = Clock::now();
+        for (size_t j = 0; j < s.parts.size(); ++j) {
+            Request &r = *s.parts[j].r;
+            if (rc != GRIM_OK) {
+                if (!r.all_admitted) {
+                    drop_from_queue(r);
+                    r.all_admitted = true;
+                }
+                r.status = rc;
+            } else if (j < part_flags.size()) {
+                r.flags |= part_flags[j];
+            }
+            part_closed(r, now);
+        }
+        pool->release(s.dev_off, s.lay.total);
+        s.parts.clear();
+        s.busy = false;
+        if (--running_ticks == 0)
+            busy_s += secs(now - busy_since);
+        launch_s += t_launch;
+        retire_s += t_retire;
+        cv_done.notify_all();
+    }
+    ring();
+}
+
+// Retires s's tick once its completion notice has run (worker thread).  The
+// results go into each request's result area without the server lock: a
+// request's area is written only by the workers of its parts until its last
+// part is closed, and their bits meet only in shared boundary words.
+void grim_server::retire(Slot &s, double t_launch)
+{
+    const auto t0 = Clock::now();
     const uint8_t *out = s.stage + s.lay.out_base;
     const int32_t *counts = reinterpret_cast<const int32_t *>(out + s.lay.counts);
     const uint32_t *bits = reinterpret_cast<const uint32_t *>(out + s.lay.bits);
-    const uint32_t status = *reinterpret_cast<const uint32_t *>(out + s.lay.status);
+    const uint32_t status = *reinterpret_cast<const uint32_t *>(out + s.lay.ws);
     const bool bits_only = (cfg.flags & GRIM_SERVE_PASS_BITS_ONLY) != 0;
+    int rc = GRIM_OK;
     if (bits_only && (status & GRIM_FLAG_BIN_RANGE)) {
         // the counts stayed on the device: fetch this tick's to find the -1s
         uint64_t n = 0;
@@ -444,84 +587,34 @@ void grim_server::retire(Slot &s)
         const uint8_t *dout = pool_base + s.dev_off + s.lay.out_base;
         if (backend().copy_d2h(s.stage + s.lay.out_base + s.lay.counts, dout + s.lay.counts,
                                n * 4, s.stream) != GRIM_OK ||
-            backend().stream_sync(s.stream) != GRIM_OK) {
-            for (Part &pt : s.parts)  // cannot tell which: fail them all
-                pt.r->status = GRIM_E_HIP;
-        }
+            backend().stream_sync(s.stream) != GRIM_OK)
+            rc = GRIM_E_HIP;  // cannot tell which part: fail them all
     }
-    const auto now = Clock::now();
-    for (Part &pt : s.parts) {
-        Request &r = *pt.r;
+    std::vector<uint32_t> part_flags(s.parts.size(), 0);
+    for (size_t j = 0; j < s.parts.size() && rc == GRIM_OK; ++j) {
+        const Part &pt = s.parts[j];
+        const Request &r = *pt.r;
         const uint64_t np = pt.pb - pt.pa;
-        if (!r.cancelled && np) {
-            if (!bits_only && !pt.counts_direct)
-                std::memcpy(r.counts() + pt.pa, counts + pt.fused_base, np * 4);
-            or_bits(r.bits(), pt.pa, bits, pt.fused_base, np);
-            if (status & GRIM_FLAG_BIN_RANGE) {  // only then look for -1 in this part
-                const int32_t *c = bits_only ? counts + pt.fused_base : r.counts() + pt.pa;
-                for (uint64_t k = 0; k < np; ++k)
-                    if (c[k] < 0) {
-                        r.flags |= GRIM_FLAG_BIN_RANGE;
-                        break;
-                    }
-            }
+        if (!np)
+            continue;
+        if (!bits_only && !pt.counts_direct)
+            std::memcpy(r.counts() + pt.pa, counts + pt.fused_base, np * 4);
+        put_bits(r.bits(), pt.pa, bits, pt.fused_base, np);
+        if (status & GRIM_FLAG_BIN_RANGE) {  // only then look for -1 in this part
+            const int32_t *c = bits_only ? counts + pt.fused_base : r.counts() + pt.pa;
+            for (uint64_t k = 0; k < np; ++k)
+                if (c[k] < 0) {
+                    part_flags[j] = GRIM_FLAG_BIN_RANGE;
+                    break;
+                }
         }
-        part_closed(r, now);
     }
-    pool->release(s.dev_off, s.lay.total);
-    s.parts.clear();
-    s.busy = false;
-    s.finished.store(false, std::memory_order_relaxed);
-    if (--running_ticks == 0)
-        busy_s += std::chrono::duration<double>(now - busy_since).count();
-    cv_done.notify_all();
+    close_tick(s, rc, part_flags, t_launch, secs(Clock::now() - t0));
 }
 
-namespace {
-
-// Queues the H2D copies of one array section: every request's slice of `bytes`
-// goes to dev + sec_off + slice offset; large slices by DMA from the request's
-// block, consecutive small slices packed in the stage and sent as one run.
-struct SectionCopier {
-    uint8_t *dev, *stage;
-    void *s;
-    uint64_t run_lo = 0, run_hi = 0;
-    bool run = false;
-    int err = GRIM_OK;
-
-    void flush()
-    {
-        if (run && run_hi > run_lo && err == GRIM_OK)
-            err = backend().copy_h2d(dev + run_lo, stage + run_lo, run_hi - run_lo, s);
-        run = false;
-    }
-    void add(uint64_t off, const void *src, uint64_t bytes)
-    {
-        if (!bytes)
-            return;
-        if (bytes >= kDirectBytes) {
-            flush();
-            if (err == GRIM_OK)
-                err = backend().copy_h2d(dev + off, src, bytes, s);
-            return;
-        }
-        std::memcpy(stage + off, src, bytes);
-        if (run && off == run_hi) {
-            run_hi = off + bytes;
-        } else {
-            flush();
-            run = true;
-            run_lo = off;
-            run_hi = off + bytes;
-        }
-    }
-};
-
-}  // namespace
-
-// Form and launch one tick on a free slot.  Returns false if nothing could be
-// launched.  Called with mu held; drops it while staging.
-bool grim_server::launch_tick(std::unique_lock<std::mutex> &lk)
+// Forms one tick on a free slot and hands it to the slot's worker.  Returns
+// false if nothing could be admitted.  Admission thread, mu held.
+bool grim_server::admit_tick()
 {
     Slot *slot = nullptr;
     for (auto &s : slots)
@@ -585,15 +678,27 @@ bool grim_server::launch_tick(std::unique_lock<std::mutex> &lk)
             }
             const uint64_t *ro = r.read_off();
             const uint32_t *rl = r.read_len();
+            // the packed words reads [ra, rb) span; the layout check per read
+            // only when the whole range does not fit
             uint64_t lo = ~0ull, hi = 0, end = pt.ra;
             for (uint64_t i = pt.ra; i < rb; ++i) {
-                const uint64_t nlo = std::min<uint64_t>(lo, ro[i] >> 4);
-                const uint64_t nhi = std::max<uint64_t>(hi, (ro[i] + rl[i] + 15) >> 4);
-                if (!fits(nhi - nlo, i + 1 - pt.ra, co[i + 1] - co[pt.ra]))
-                    break;
-                lo = nlo;
-                hi = nhi;
-                end = i + 1;
+                lo = std::min<uint64_t>(lo, ro[i] >> 4);
+                hi = std::max<uint64_t>(hi, (ro[i] + rl[i] + 15) >> 4);
+            }
+            if (fits(hi - lo, rb - pt.ra, co[rb] - co[pt.ra])) {
+                end = rb;
+            } else {
+                lo = ~0ull;
+                hi = 0;
+                for (uint64_t i = pt.ra; i < rb; ++i) {
+                    const uint64_t nlo = std::min<uint64_t>(lo, ro[i] >> 4);
+                    const uint64_t nhi = std::max<uint64_t>(hi, (ro[i] + rl[i] + 15) >> 4);
+                    if (!fits(nhi - nlo, i + 1 - pt.ra, co[i + 1] - co[pt.ra]))
+                        break;
+                    lo = nlo;
+                    hi = nhi;
+                    end = i + 1;
+                }
             }
             if (end == pt.ra)  // not one more read fits: wait for memory
                 break;
@@ -642,30 +747,119 @@ bool grim_server::launch_tick(std::unique_lock<std::mutex> &lk)
         r.all_admitted = pt.rb == r.n_reads;
         ++r.parts_open;
     }
-    slot->busy = true;
-    slot->finished.store(false, std::memory_order_relaxed);
-    slot->lay = lay;
-    slot->dev_off = off;
-    slot->tick = tick;
     if (running_ticks++ == 0)
         busy_since = now;
     ++ticks;
     reqs_in_ticks += take.size();
+    slot->busy = true;
+    slot->parts = std::move(take);
+    slot->lay = lay;
+    slot->dev_off = off;
+    slot->tick = tick;
+    slot->e_den = e_den;
+    {
+        std::lock_guard<std::mutex> lk(slot->m);
+        slot->job = true;
+    }
+    slot->cv.notify_one();
+    return true;
+}
 
-    lk.unlock();
+namespace {
+
+// Plans the copies of one region of a tick (inputs host to device, or outputs
+// device to host), slice by slice in increasing offset order.  A slice of at
+// least kDirectBytes moves by DMA between the request's own memory and the
+// device; smaller slices go through the slot's stage, and staged slices less
+// than 256 bytes apart (alignment gaps) are sent as one copy, so that a tick
+// of small requests needs one copy each way.
+struct RunCopier {
+    uint8_t *dev, *stage;
+    bool h2d;
+    std::vector<CopyOp> ops;
+    uint64_t run_lo = 0, run_hi = 0;
+    bool run = false;
+
+    RunCopier(uint8_t *dev_, uint8_t *stage_, bool h2d_) : dev(dev_), stage(stage_), h2d(h2d_) {}
+
+    void add(uint64_t off, uint8_t *host, uint64_t bytes)
+    {
+        if (h2d)
+            ops.push_back({dev + off, host, bytes});
+        else
+            ops.push_back({host, dev + off, bytes});
+    }
+    void flush()
+    {
+        if (run)
+            add(run_lo, stage + run_lo, run_hi - run_lo);
+        run = false;
+    }
+    // [off, off + bytes) of the stage holds the slice (to device) or receives it
+    void staged(uint64_t off, uint64_t bytes)
+    {
+        if (!bytes)
+            return;
+        if (run && off >= run_hi && off - run_hi <= 256) {
+            run_hi = off + bytes;
+            return;
+        }
+        flush();
+        run = true;
+        run_lo = off;
+        run_hi = off + bytes;
+    }
+    // the slice at off moves straight between `host` and the device
+    void direct(uint64_t off, void *host, uint64_t bytes)
+    {
+        flush();
+        add(off, static_cast<uint8_t *>(host), bytes);
+    }
+    // a host slice to the device: by DMA when large, else through the stage
+    void put(uint64_t off, const void *src, uint64_t bytes)
+    {
+        if (bytes >= kDirectBytes) {
+            direct(off, const_cast<void *>(src), bytes);
+        } else if (bytes) {
+            std::memcpy(stage + off, src, bytes);
+            staged(off, bytes);
+        }
+    }
+    // queue the planned copies on stream s
+    int issue(void *s) const
+    {
+        for (const CopyOp &op : ops) {
+            const int e = h2d ? backend().copy_h2d(op.dst, op.src, op.bytes, s)
+                              : backend().copy_d2h(op.dst, op.src, op.bytes, s);
+            if (e != GRIM_OK)
+                return GRIM_E_HIP;
+        }
+        return GRIM_OK;
+    }
+};
+
+}  // namespace
+
+// Stages s's tick and queues it on the slot's stream (worker thread, no server
+// lock): the input copies, the filter, the result copies and last the
+// completion notice.  On failure, waits for what was queued and returns the
+// error.
+int grim_server::launch(Slot &s)
+{
     const grim_serve::Backend &be = backend();
-    int rc = GRIM_OK;
-    uint8_t *h = slot->stage;
-    uint8_t *d = pool_base + off;
-    void *st = slot->stream;
-    SectionCopier cw{d, h, st}, cl{d, h, st}, ce{d, h, st}, cb{d, h, st};
+    const Layout &lay = s.lay;
+    uint8_t *h = s.stage;
+    uint8_t *d = pool_base + s.dev_off;
+    void *st = s.stream;
+    // per-read arrays, re-based to the fused tick
     uint64_t wbase = 0, rbase = 0, pbase = 0;
     uint64_t *ro = reinterpret_cast<uint64_t *>(h + lay.read_off);
     uint64_t *coff = reinterpret_cast<uint64_t *>(h + lay.cand_off);
-    for (auto &pt : take) {
-        Request &r = *pt.r;
-        const uint64_t nr = pt.rb - pt.ra, np = pt.pb - pt.pa;
-        cw.add(lay.words + wbase * 4, r.words() + pt.wlo, pt.nw * 4);
+    uint32_t *rlen = reinterpret_cast<uint32_t *>(h + lay.read_len);
+    uint32_t *re = reinterpret_cast<uint32_t *>(h + lay.read_e);
+    for (Part &pt : s.parts) {
+        const Request &r = *pt.r;
+        const uint64_t nr = pt.rb - pt.ra;
         const uint64_t *sro = r.read_off(), *sco = r.cand_off();
         const uint64_t shift = wbase * 16, base0 = pt.wlo * 16;
         for (uint64_t i = 0; i < nr; ++i) {
@@ -673,38 +867,57 @@ bool grim_server::launch_tick(std::unique_lock<std::mutex> &lk)
             coff[rbase + i] = sco[pt.ra + i] - pt.pa + pbase;
         }
         if (nr) {
-            cl.add(lay.read_len + rbase * 4, r.read_len() + pt.ra, nr * 4);
-            ce.add(lay.read_e + rbase * 4, r.read_e() + pt.ra, nr * 4);
+            std::memcpy(rlen + rbase, r.read_len() + pt.ra, nr * 4);
+            std::memcpy(re + rbase, r.read_e() + pt.ra, nr * 4);
         }
-        if (np)
-            cb.add(lay.cand_bin + pbase * 4, r.cand_bin() + pt.pa, np * 4);
         pt.fused_base = pbase;
         wbase += pt.nw;
         rbase += nr;
-        pbase += np;
+        pbase += pt.pb - pt.pa;
     }
     coff[rbase] = pbase;
-    const uint32_t zero = 0;
-    cw.add(lay.words + wbase * 4, &zero, 4);  // trailing word read by tokens at the end
-    cw.flush();
-    cl.flush();
-    ce.flush();
-    cb.flush();
-    int e = cw.err != GRIM_OK ? cw.err : cl.err != GRIM_OK ? cl.err : ce.err != GRIM_OK ? ce.err
-          : cb.err;
-    if (e == GRIM_OK)
-        e = be.copy_h2d(d + lay.read_off, h + lay.read_off, rbase * 8, st);
-    if (e == GRIM_OK)
-        e = be.copy_h2d(d + lay.cand_off, h + lay.cand_off, (rbase + 1) * 8, st);
-    if (e != GRIM_OK)
-        rc = GRIM_E_HIP;
+    RunCopier in{d, h, true};
+    in.staged(lay.read_off, rbase * 8);
+    in.staged(lay.cand_off, (rbase + 1) * 8);
+    in.staged(lay.read_len, rbase * 4);
+    in.staged(lay.read_e, rbase * 4);
+    // packed words, then bin ids (no token reaches past a read's last base, so
+    // nothing after the words needs to be written)
+    uint64_t o = lay.words;
+    for (const Part &pt : s.parts) {
+        in.put(o, pt.r->words() + pt.wlo, pt.nw * 4);
+        o += pt.nw * 4;
+    }
+    for (const Part &pt : s.parts)
+        in.put(lay.cand_bin + pt.fused_base * 4, pt.r->cand_bin() + pt.pa, (pt.pb - pt.pa) * 4);
+    in.flush();
+    // with upload turns: wait for this tick's turn, queue the input copies,
+    // then the notice that ends the turn once they have run (or end it here if
+    // that notice could not be queued)
+    s.turn_wait_s = 0;
+    if (upload_turns) {
+        const auto t0 = Clock::now();
+        std::unique_lock<std::mutex> lk(up_mu);
+        const uint64_t mine = up_next++;
+        up_cv.wait(lk, [&] { return up_turn == mine; });
+        s.turn_wait_s = secs(Clock::now() - t0);
+    }
+    int rc = in.issue(st);
+    if (upload_turns) {
+        if (rc == GRIM_OK && be.notify(st, on_upload_done, &s) != GRIM_OK)
+            rc = GRIM_E_HIP;
+        if (rc != GRIM_OK) {
+            (void)be.stream_sync(st);
+            upload_turn_end();
+        }
+    }
     grim_batch_t b;
     b.reads_2bit = reinterpret_cast<const uint32_t *>(d + lay.words);
-    b.n_read_words = wbase + 1;
+    b.n_read_words = std::max<uint64_t>(wbase, 1);  // the layout holds one word more
     b.read_off = reinterpret_cast<const uint64_t *>(d + lay.read_off);
     b.read_len = reinterpret_cast<const uint32_t *>(d + lay.read_len);
     b.read_e = reinterpret_cast<const uint32_t *>(d + lay.read_e);
-    b.e_den = e_den;
+    b.e_den = s.e_den;
     b.max_len = cfg.max_len;
     b.cand_off = reinterpret_cast<const uint64_t *>(d + lay.cand_off);
     b.cand_bin = reinterpret_cast<const uint32_t *>(d + lay.cand_bin);
@@ -715,80 +928,68 @@ bool grim_server::launch_tick(std::unique_lock<std::mutex> &lk)
     int32_t *dcounts = reinterpret_cast<int32_t *>(dout + lay.counts);
     uint32_t *dbits = reinterpret_cast<uint32_t *>(dout + lay.bits);
     if (rc == GRIM_OK)
-        rc = be.filter(idx, &b, dcounts, dbits, d + lay.ws, lay.ws_bytes, st);
+        rc = be.filter(idx, &b, dcounts, dbits, dout + lay.ws, lay.ws_bytes, st);
     // results: large count slices straight into the request's result area, the
-    // rest (small slices, all pass bits, the status word) via the stage; no
-    // counts at all when only the pass bits are results; then the completion
-    // notice
+    // rest (small slices, then the pass bits with the status word that follows
+    // them) via the stage; no counts at all when only the pass bits are
+    // results; then the completion notice
     if (rc == GRIM_OK) {
         const bool bits_only = (cfg.flags & GRIM_SERVE_PASS_BITS_ONLY) != 0;
-        uint64_t run_lo = 0, run_hi = 0;
-        bool run = false;
-        auto flush = [&] {
-            if (run && e == GRIM_OK)
-                e = be.copy_d2h(hout + run_lo, dout + run_lo, run_hi - run_lo, st);
-            run = false;
-        };
-        for (size_t j = 0; j < take.size() && e == GRIM_OK && !bits_only; ++j) {
-            Part &pt = take[j];
+        RunCopier out{dout, hout, false};
+        for (size_t j = 0; j < s.parts.size() && !bits_only; ++j) {
+            Part &pt = s.parts[j];
             const uint64_t lo = lay.counts + pt.fused_base * 4, nb = (pt.pb - pt.pa) * 4;
             if (nb >= kDirectBytes) {
-                flush();
-                e = be.copy_d2h(pt.r->counts() + pt.pa, dout + lo, nb, st);
+                out.direct(lo, pt.r->counts() + pt.pa, nb);
                 pt.counts_direct = true;
-            } else if (nb) {
-                if (run && lo == run_hi) {
-                    run_hi = lo + nb;
-                } else {
-                    flush();
-                    run = true;
-                    run_lo = lo;
-                    run_hi = lo + nb;
-                }
+            } else {
+                out.staged(lo, nb);
             }
         }
-        flush();
-        if (e == GRIM_OK)
-            e = be.copy_d2h(hout + lay.bits, dout + lay.bits, ((pbase + 31) / 32) * 4 + 4, st);
-        if (e == GRIM_OK)  // status word of this launch
-            e = be.copy_d2h(hout + lay.status, d + lay.ws, 4, st);
-        if (e != GRIM_OK)
+        out.staged(lay.bits, lay.ws - lay.bits + 4);
+        out.flush();
+        rc = out.issue(st);
+        if (rc == GRIM_OK && be.notify(st, on_tick_done, &s) != GRIM_OK)  // last: may run at once
             rc = GRIM_E_HIP;
     }
-    lk.lock();
-    if (rc == GRIM_OK) {
-        slot->parts = std::move(take);
-        // queued last, with the tick's parts in place: the notice may run at once
-        if (be.notify(st, on_tick_done, slot) == GRIM_OK)
-            return true;
-        rc = GRIM_E_HIP;
-        take = std::move(slot->parts);
-        slot->parts.clear();
-    }
-    // the tick never completed on the device: fail its requests (a request
-    // with reads still queued is dropped from the queue)
-    (void)be.stream_sync(slot->stream);
-    const auto t = Clock::now();
-    for (auto &pt : take) {
-        Request &r = *pt.r;
-        if (!r.all_admitted) {
-            drop_from_queue(r);
-            r.all_admitted = true;
-        }
-        r.status = rc;
-        part_closed(r, t);
-    }
-    pool->release(off, lay.total);
-    slot->busy = false;
-    if (--running_ticks == 0)
-        busy_s += std::chrono::duration<double>(t - busy_since).count();
-    cv_done.notify_all();
-    return true;
+    if (rc != GRIM_OK)
+        (void)be.stream_sync(st);  // the tick never completes: let what was queued finish
+    return rc;
 }
 
-void grim_server::run()
+// A slot's worker: takes each tick the admission thread hands over, launches
+// it, waits for its completion notice and retires it.
+void grim_server::work(Slot &s)
 {
     backend().set_device(device);
+    for (;;) {
+        {
+            std::unique_lock<std::mutex> lk(s.m);
+            s.cv.wait(lk, [&] { return s.job || s.quit; });
+            if (!s.job)
+                return;
+            s.job = false;
+            s.notice = false;
+        }
+        const auto t0 = Clock::now();
+        const int rc = launch(s);
+        const double t_launch = secs(Clock::now() - t0) - s.turn_wait_s;
+        if (rc != GRIM_OK) {
+            close_tick(s, rc, {}, t_launch, 0.0);
+            continue;
+        }
+        {
+            std::unique_lock<std::mutex> lk(s.m);
+            s.cv.wait(lk, [&] { return s.notice; });
+        }
+        retire(s, t_launch);
+    }
+}
+
+// The admission thread: forms ticks while slots are free and requests wait,
+// then sleeps until the doorbell rings.  Ends on shutdown once no tick runs.
+void grim_server::run()
+{
     std::unique_lock<std::mutex> lk(mu);
     for (;;) {
         uint64_t seen;
@@ -796,22 +997,13 @@ void grim_server::run()
             std::lock_guard<std::mutex> bl(bell_mu);
             seen = bell;  // a ring after this point wakes the wait below
         }
-        for (auto &s : slots)
-            if (s->busy && s->finished.load(std::memory_order_acquire)) {
-                const auto t0 = Clock::now();
-                retire(*s);
-                retire_s += std::chrono::duration<double>(Clock::now() - t0).count();
-            }
         if (stop && running_ticks == 0)
             break;
         if (!stop) {
-            for (;;) {
-                const auto t0 = Clock::now();
-                const bool launched = launch_tick(lk);
-                if (!launched)
-                    break;
-                launch_s += std::chrono::duration<double>(Clock::now() - t0).count();
+            const auto t0 = Clock::now();
+            while (admit_tick()) {
             }
+            admit_s += secs(Clock::now() - t0);
         }
         lk.unlock();
         {
@@ -827,15 +1019,14 @@ void grim_server::run()
 
 namespace {
 
-// Frees what grim_serve_create has set up so far (no scheduler thread yet).
+// Frees what grim_serve_create has set up so far (no thread started yet).
 void free_server_parts(grim_server *s)
 {
     const grim_serve::Backend &be = backend();
-    for (auto &sl : s->slots) {
-        if (sl->stream)
-            be.stream_destroy(sl->stream);
+    for (auto &sl : s->slots)
         be.pinned_free(sl->stage);
-    }
+    for (void *st : s->streams)
+        be.stream_destroy(st);
     be.pinned_free(s->arena);
     be.device_free(s->pool_base);
 }
@@ -858,7 +1049,10 @@ extern "C" int grim_serve_create(const grim_index_t *idx, const grim_serve_cfg_t
         c.max_tick_pairs = 8u << 20;
     if (!c.max_len)
         c.max_len = 1024;
-    if (c.max_len > GRIM_MAX_READ_LEN || c.n_streams > 16 ||
+    const bool bits_only = (c.flags & GRIM_SERVE_PASS_BITS_ONLY) != 0;
+    if (!c.ticks_per_stream)
+        c.ticks_per_stream = bits_only ? 2 : 1;
+    if (c.max_len > GRIM_MAX_READ_LEN || c.n_streams > 16 || c.ticks_per_stream > 4 ||
         (c.flags & ~GRIM_SERVE_PASS_BITS_ONLY))
         return GRIM_E_INVALID;
     const grim_serve::Backend &be = backend();
@@ -869,6 +1063,7 @@ extern "C" int grim_serve_create(const grim_index_t *idx, const grim_serve_cfg_t
     s->idx = idx;
     s->cfg = c;
     s->device = dev;
+    s->upload_turns = !bits_only;
     if (be.device_alloc(c.hbm_budget_bytes, &s->pool_base) != GRIM_OK)
         return GRIM_E_NOMEM;
     s->pool = std::make_unique<Pool>(c.hbm_budget_bytes);
@@ -888,15 +1083,20 @@ extern "C" int grim_serve_create(const grim_index_t *idx, const grim_serve_cfg_t
     const uint64_t R = std::max<uint64_t>(4096, P / 32);
     const uint64_t W = R * (c.max_len / 16 + 2) + 1;
     s->stage_bytes = std::min<uint64_t>(c.hbm_budget_bytes, plan(W, R, P, ws_need(idx, P)).total);
-    s->slots.resize(c.n_streams);
-    for (auto &sl : s->slots) {
-        sl = std::make_unique<Slot>();
-        sl->srv = s.get();
-        if (be.stream_create(&sl->stream) != GRIM_OK) {
-            sl->stream = nullptr;
+    for (uint32_t i = 0; i < c.n_streams; ++i) {
+        void *st = nullptr;
+        if (be.stream_create(&st) != GRIM_OK) {
             free_server_parts(s.get());
             return GRIM_E_HIP;
         }
+        s->streams.push_back(st);
+    }
+    s->slots.resize((size_t)c.ticks_per_stream * c.n_streams);
+    for (size_t i = 0; i < s->slots.size(); ++i) {
+        auto &sl = s->slots[i];
+        sl = std::make_unique<Slot>();
+        sl->srv = s.get();
+        sl->stream = s->streams[i % c.n_streams];
         if (be.pinned_alloc(s->stage_bytes, &sl->stage) != GRIM_OK) {
             sl->stage = nullptr;
             free_server_parts(s.get());
@@ -905,6 +1105,10 @@ extern "C" int grim_serve_create(const grim_index_t *idx, const grim_serve_cfg_t
         sl->stage_bytes = s->stage_bytes;
     }
     grim_server *raw = s.release();
+    for (auto &sl : raw->slots) {
+        Slot *p = sl.get();
+        p->worker = std::thread([raw, p] { raw->work(*p); });
+    }
     raw->thr = std::thread([raw] { raw->run(); });
     *out = raw;
     return GRIM_OK;
@@ -1183,6 +1387,7 @@ extern "C" int grim_serve_stats(grim_server_t *s, grim_serve_stats_t *out, int r
     out->pairs_per_s = busy > 0 ? s->pairs_done / busy : 0.0;
     out->peak_device_bytes = s->peak_bytes;
     out->mean_requests_per_tick = s->ticks ? (double)s->reqs_in_ticks / s->ticks : 0.0;
+    out->sched_admit_s = s->admit_s;
     out->sched_launch_s = s->launch_s;
     out->sched_retire_s = s->retire_s;
     if (reset) {
@@ -1191,7 +1396,7 @@ extern "C" int grim_serve_stats(grim_server_t *s, grim_serve_stats_t *out, int r
         s->peak_bytes = s->pool->used();
         s->lat.clear();
         s->busy_s = 0;
-        s->launch_s = s->retire_s = 0;
+        s->admit_s = s->launch_s = s->retire_s = 0;
         if (s->running_ticks > 0)
             s->busy_since = Clock::now();
     }
@@ -1214,11 +1419,21 @@ extern "C" void grim_serve_destroy(grim_server_t *s)
     s->ring();
     if (s->thr.joinable())
         s->thr.join();
-    // every tick has been retired; wait until the streams (and the completion
-    // notices on them) have finished before the server's memory goes
+    // every tick has been retired: the workers wait for work; end them
+    for (auto &sl : s->slots) {
+        {
+            std::lock_guard<std::mutex> lk(sl->m);
+            sl->quit = true;
+        }
+        sl->cv.notify_one();
+        if (sl->worker.joinable())
+            sl->worker.join();
+    }
+    // wait until the streams (and the completion notices on them) have
+    // finished before the server's memory goes
     const grim_serve::Backend &be = backend();
-    for (auto &sl : s->slots)
-        (void)be.stream_sync(sl->stream);
+    for (void *st : s->streams)
+        (void)be.stream_sync(st);
     for (auto &kv : s->all)
         s->free_block(*kv.second);
     s->all.clear();

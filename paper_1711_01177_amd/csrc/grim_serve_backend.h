@@ -11,7 +11,8 @@
 //   - notify(s, fn, arg) calls fn(arg) once every operation queued on s before
 //     it has completed (results of earlier copies are then visible to the
 //     host); fn runs on a thread of the implementation, must not block and must
-//     not call back into the backend.
+//     not call back into the backend;
+//   - enqueueing on one stream from several threads is allowed.
 #pragma once
 
 #include <stdint.h>

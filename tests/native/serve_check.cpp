@@ -4,7 +4,9 @@
 //
 // Scenarios: requests from several submitting threads, copied and in place,
 // split into parts and fused into ticks, cancelled concurrently from another
-// thread; the same with injected filter-launch failures; a pass-bits-only
+// thread, with one or more ticks queued per stream; the same with injected
+// filter-launch failures; large requests whose slices move by DMA instead of
+// through the stage; a pass-bits-only
 // server with an out-of-range bin; requests refused at submit; a server
 // destroyed with work queued.  After each scenario every ticket must have
 // ended with an allowed status, every finished request's results must equal
@@ -287,6 +289,13 @@ void refusals(grim_index_t *idx)
     b = big.batch();
     CHECK(grim_serve_submit(srv, &b, &tk) == GRIM_E_BUDGET);
     grim_serve_destroy(srv);
+    // configurations out of range
+    grim_serve_cfg_t bad = cfg;
+    bad.ticks_per_stream = 5;
+    CHECK(grim_serve_create(idx, &bad, &srv) == GRIM_E_INVALID);
+    bad = cfg;
+    bad.n_streams = 17;
+    CHECK(grim_serve_create(idx, &bad, &srv) == GRIM_E_INVALID);
     std::printf("refusals: ok\n");
 }
 
@@ -327,8 +336,9 @@ int main()
     Scenario base{"mix", mix, 4, 40, 300, 0, 0, 0};
     run(base, idx, 1);
     Scenario cancels = base;
-    cancels.name = "mix with cancellations";
+    cancels.name = "mix with cancellations, two ticks per stream";
     cancels.cancel_every = 3;
+    cancels.cfg.ticks_per_stream = 2;
     run(cancels, idx, 2);
     Scenario faults = cancels;
     faults.name = "mix with failed launches and cancellations";
@@ -348,6 +358,16 @@ int main()
     wide.cfg.hbm_budget_bytes = 64ull << 20;
     wide.bad_every = 5;
     run(wide, idx, 5);
+    Scenario big = cancels;
+    big.name = "large requests: slices moved by DMA, split over three streams, three ticks each";
+    big.cfg.ticks_per_stream = 3;
+    big.cfg.max_tick_pairs = 100000;
+    big.cfg.hbm_budget_bytes = 64ull << 20;
+    big.threads = 2;
+    big.per_thread = 5;
+    big.max_reads = 3000;
+    big.bad_every = 4;
+    run(big, idx, 6);
     refusals(idx);
     destroy_with_work_queued(idx);
     CHECK(fake_device_bytes() == dev0);  // every server's pool was freed
