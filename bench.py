@@ -488,6 +488,31 @@ def window_leg(g, idx, w, torch, stream, rng, window_bins=4096, n_reads=200_000,
     same_sorted = bool(torch.equal(cs[:n].view(n_reads, window_bins),
                                    c1[:n].view(n_reads, window_bins)[tperm]))
     del cs, bs, sb, swl, tperm
+    # the reads in index order, processed in the device-side order (reads
+    # grouped by window-start bucket): the order and the filter timed together
+    co, bo = g.alloc_outputs(n)
+    order_ws = torch.empty(g.grim_window_order_workspace_size(idx, n_reads), dtype=torch.uint8,
+                           device="cuda")
+    order = torch.empty(n_reads, dtype=torch.int32, device="cuda")
+    g.grim_window_order(idx, wl, order=order, workspace=order_ws)
+    g.grim_filter_windows(idx, wb, wl, co, bo, ws, order=order)
+    rc_order, _ = g.grim_filter_status(ws)
+    e0.record(stream)
+    for _ in range(5):
+        g.grim_window_order(idx, wl, order=order, workspace=order_ws)
+        g.grim_filter_windows(idx, wb, wl, co, bo, ws, order=order)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_order = e0.elapsed_time(e1) / 5
+    e0.record(stream)
+    for _ in range(5):
+        g.grim_window_order(idx, wl, order=order, workspace=order_ws)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_order_only = e0.elapsed_time(e1) / 5
+    same_order = bool(torch.equal(co[:n], c1[:n]) and
+                      torch.equal(bo[:(n + 31) // 32], b1[:(n + 31) // 32]))
+    del co, bo, order, order_ws
     # the same pairs as explicit candidates through the batched kernel
     cb = (lo.astype(np.int64)[:, None] + np.arange(window_bins)[None, :]).astype(np.uint32).ravel()
     eb = g.Batch(w["codes"][:o_end], w["read_off"][:n_reads], w["read_len"][:n_reads],
@@ -515,6 +540,12 @@ def window_leg(g, idx, w, torch, stream, rng, window_bins=4096, n_reads=200_000,
                unaligned=dict(ms=ms_unaligned, pairs_per_s=n / (ms_unaligned * 1e-3),
                               status=rc_unaligned,
                               algorithmic_gbs=n_reads * row_bytes / (ms_unaligned * 1e-3) / 1e9),
+               device_order=dict(note="index-order reads processed in the order of "
+                                      "grim_window_order (reads grouped by window-start "
+                                      "bucket); order + filter timed together",
+                                 ms=ms_order, order_ms=ms_order_only,
+                                 pairs_per_s=n / (ms_order * 1e-3), status=rc_order,
+                                 identical=same_order),
                presorted=dict(note="the same reads submitted sorted by window start "
                                    "(host argsort outside the timing)",
                               ms=ms_sorted, pairs_per_s=n / (ms_sorted * 1e-3),
@@ -800,7 +831,9 @@ def main():
             f"{window['ms']:.3f} ms -> {window['pairs_per_s']:.3e} pairs/s "
             f"(batched random-gather form: {pairs_per_s:.3e}); identical={window['identical']}; "
             f"reads pre-sorted by window: {window['presorted']['ms']:.3f} ms, "
-            f"identical={window['presorted']['identical_per_read_bin']}")
+            f"identical={window['presorted']['identical_per_read_bin']}; device order + filter: "
+            f"{window['device_order']['ms']:.3f} ms (order {window['device_order']['order_ms']:.3f} ms), "
+            f"identical={window['device_order']['identical']}")
 
     cpu, parity = None, None
     if not args.no_cpu:

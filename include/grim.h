@@ -295,21 +295,31 @@ int grim_index_transpose(grim_index_t *idx, void *stream);
  * [win_lo[r], win_lo[r] + (cand_off[r+1] - cand_off[r])), and pair
  * cand_off[r] + j is bin win_lo[r] + j (b->cand_bin is not used).  Outputs,
  * status and errors as grim_filter_batch (a bin >= n_bins gives -1 and
- * GRIM_FLAG_BIN_RANGE).  win_lo: device u32[n_reads].  order: must be NULL
- * (reads are processed in index order); a processing order is switched off
- * in this version and gives GRIM_E_UNSUPPORTED.  workspace: device, >= 256
- * bytes, 256-byte aligned.  Needs grim_index_transpose first (else GRIM_E_INVALID);
- * b->max_len <= 4096 (else GRIM_E_UNSUPPORTED).  Asynchronous on `stream`;
- * allocates nothing. */
+ * GRIM_FLAG_BIN_RANGE).  win_lo: device u32[n_reads].  order: NULL (reads are
+ * processed in index order) or device u32[n_reads], the order in which reads
+ * are processed (grim_window_order gives one); outputs do not depend on it.  An
+ * entry >= n_reads is skipped and sets GRIM_FLAG_READ (GRIM_E_READ from
+ * grim_filter_status); a read named by no entry keeps the previous contents of
+ * its counts.  workspace: device, >= 256 bytes, 256-byte aligned.  Needs
+ * grim_index_transpose first (else GRIM_E_INVALID); b->max_len <= 4096 (else
+ * GRIM_E_UNSUPPORTED).  Asynchronous on `stream`; allocates nothing. */
 int grim_filter_windows(const grim_index_t *idx, const grim_batch_t *b, const uint32_t *win_lo,
                         const uint32_t *order, int32_t *counts, uint32_t *pass_bits,
                         void *workspace, uint64_t workspace_bytes, void *stream);
 
-/* Device-side processing order for grim_filter_windows (the stable argsort
- * of win_lo, so that reads with overlapping windows run together and share
- * row segments through the cache).  Switched off in this version: both calls
- * return GRIM_E_UNSUPPORTED and write nothing (bytes is set to 0).  A caller
- * gets the same cache sharing by submitting its reads sorted by window start. */
+/* Device-side processing order for grim_filter_windows (Section "GRIM-Filter
+ * Parallelization": windows of consecutive bins processed together): a
+ * permutation of the n_reads reads grouped by the bucket of their window start,
+ * buckets in increasing order, where bucket k holds starts in
+ * [k * 2^s, (k + 1) * 2^s) with 2^s = 1024 bins, or more for indexes of over
+ * 2^26 bins so that there are at most 2^16 buckets; starts >= n_bins come last.
+ * Reads with overlapping windows then run close together and share row
+ * segments through the cache.  The order of reads within a bucket is
+ * unspecified and may differ between calls.  win_lo, order: device
+ * u32[n_reads]; workspace: device, grim_window_order_workspace_size(...) bytes
+ * (the bucket counts), 4-byte aligned.  GRIM_E_INVALID for NULL pointers, a
+ * small workspace or a device other than the index's; GRIM_E_UNSUPPORTED for
+ * n_reads >= 2^32.  Asynchronous on `stream`; allocates nothing. */
 int grim_window_order_workspace_size(const grim_index_t *idx, uint64_t n_reads, uint64_t *bytes);
 int grim_window_order(const grim_index_t *idx, const uint32_t *win_lo, uint64_t n_reads,
                       uint32_t *order, void *workspace, uint64_t workspace_bytes, void *stream);

@@ -499,8 +499,8 @@ def grim_verify_survivors(index, batch, surv_read, surv_bin, n=None, stream=None
 def grim_filter_windows(index, batch, win_lo, counts, pass_bits, workspace, stream=None,
                         order=None):
     """Bin-window filter: every bin of [win_lo[r], win_lo[r] + window size).
-    order must stay None: processing orders are switched off in the library
-    (a non-None order raises GrimError with GRIM_E_UNSUPPORTED)."""
+    order: None (index order) or a device int32/uint32 tensor of n_reads read
+    ids giving the processing order (grim_window_order makes one)."""
     _check(_lib.grim_filter_windows(index.handle, ctypes.byref(batch.c), _ptr(win_lo),
                                     _ptr(order) if order is not None else None,
                                     _ptr(counts), _ptr(pass_bits), _ptr(workspace),
@@ -515,8 +515,9 @@ def grim_window_order_workspace_size(index, n_reads):
 
 
 def grim_window_order(index, win_lo, order=None, workspace=None, stream=None):
-    """Processing order for grim_filter_windows (the stable argsort of win_lo).
-    Switched off in the library: raises GrimError with GRIM_E_UNSUPPORTED."""
+    """Processing order for grim_filter_windows: the reads grouped by the
+    bucket of their window start (1024-bin buckets, increasing; order within a
+    bucket unspecified)."""
     import torch
     n = int(win_lo.numel())
     if order is None:

@@ -835,8 +835,6 @@ extern "C" int grim_filter_windows(const grim_index_t *idx, const grim_batch_t *
 {
     if (!idx || !b)
         return GRIM_E_INVALID;
-    if (order)  // processing orders are switched off
-        return GRIM_E_UNSUPPORTED;
     if (b->e_den == 0 || b->max_len == 0 || (b->n_reads == 0 && b->n_pairs != 0))
         return GRIM_E_INVALID;
     if (b->max_len > 4096)
@@ -872,6 +870,7 @@ extern "C" int grim_filter_windows(const grim_index_t *idx, const grim_batch_t *
     a.max_len = b->max_len;
     a.cand_off = b->cand_off;
     a.win_lo = win_lo;
+    a.order = order;
     a.n_reads = b->n_reads;
     a.n_pairs = b->n_pairs;
     a.counts = counts;
@@ -889,30 +888,46 @@ extern "C" int grim_filter_windows(const grim_index_t *idx, const grim_batch_t *
     return GRIM_OK;
 }
 
-// Device-side processing orders for the window filter are switched off: both
-// entry points report GRIM_E_UNSUPPORTED.
 extern "C" int grim_window_order_workspace_size(const grim_index_t *idx, uint64_t n_reads,
                                                 uint64_t *bytes)
 {
-    (void)idx;
     (void)n_reads;
-    if (bytes)
-        *bytes = 0;
-    return GRIM_E_UNSUPPORTED;
+    if (!idx || !bytes)
+        return GRIM_E_INVALID;
+    uint32_t n_buckets = 0;
+    order_shift(idx->n_bins, &n_buckets);
+    *bytes = std::max<uint64_t>(256, ((uint64_t)n_buckets * 4 + 255) & ~255ull);
+    return GRIM_OK;
 }
 
 extern "C" int grim_window_order(const grim_index_t *idx, const uint32_t *win_lo, uint64_t n_reads,
                                  uint32_t *order, void *workspace, uint64_t workspace_bytes,
                                  void *stream)
 {
-    (void)idx;
-    (void)win_lo;
-    (void)n_reads;
-    (void)order;
-    (void)workspace;
-    (void)workspace_bytes;
-    (void)stream;
-    return GRIM_E_UNSUPPORTED;
+    if (!idx)
+        return GRIM_E_INVALID;
+    if (n_reads == 0)
+        return GRIM_OK;
+    if (!win_lo || !order || !workspace)
+        return GRIM_E_INVALID;
+    if (n_reads > 0xffffffffull)
+        return GRIM_E_UNSUPPORTED;
+    uint32_t n_buckets = 0;
+    const uint32_t shift = order_shift(idx->n_bins, &n_buckets);
+    if (workspace_bytes < (uint64_t)n_buckets * 4)
+        return GRIM_E_INVALID;
+    int dev = -1;
+    int rc = current_device(&dev);
+    if (rc)
+        return rc;
+    if (dev != idx->device)
+        return GRIM_E_INVALID;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    uint32_t *cnt = reinterpret_cast<uint32_t *>(workspace);
+    HIP_TRY(launch_zero(s, cnt, n_buckets));
+    HIP_TRY(launch_window_order(s, (uint32_t)cu_count(idx->device), win_lo, (uint32_t)n_reads,
+                                idx->n_bins, shift, n_buckets, cnt, order));
+    return GRIM_OK;
 }
 
 // ---------------------------------------------------------------- probes

@@ -76,6 +76,7 @@ struct WindowArgs {
     uint32_t max_len;
     const uint64_t *cand_off;   // window sizes
     const uint32_t *win_lo;     // first bin of each read's window
+    const uint32_t *order;      // processing order (slot -> read), or null for index order
     uint64_t n_reads, n_pairs;
     int32_t *counts;
     uint32_t *pass_bits;
@@ -112,6 +113,13 @@ hipError_t launch_transpose(hipStream_t s, int q, const uint32_t *vec, uint64_t 
 // Persistent grid: as many workgroups as fit on the device's cus compute units
 // at once (at most one per read).
 hipError_t launch_window(hipStream_t s, int q, uint32_t cus, size_t lds, const WindowArgs &a);
+// Processing order for the window kernel: reads grouped by window-start bucket
+// (bins [k << shift, (k + 1) << shift) form bucket k; starts >= n_bins the last
+// of the n_buckets).  cnt: n_buckets words, zeroed by the caller.
+uint32_t order_shift(uint64_t n_bins, uint32_t *n_buckets);
+hipError_t launch_window_order(hipStream_t s, uint32_t cus, const uint32_t *win_lo, uint32_t n,
+                               uint64_t n_bins, uint32_t shift, uint32_t n_buckets, uint32_t *cnt,
+                               uint32_t *order);
 
 // Memory-ceiling probes (grim_probe.hip): the batched filter's gather of bin
 // vectors without its token work, and a streaming read.

@@ -15,6 +15,7 @@
 // position.  Each token costs one coalesced row segment for the whole window.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstring>
 #include <type_traits>
 
@@ -258,6 +259,12 @@ __global__ __launch_bounds__(256) void window_kernel(WindowArgs a)
     __shared__ uint32_t pmask[128];                 // pass bits per column
     __shared__ uint32_t next_read;
     const int t = threadIdx.x, col = t & 127, half = t >> 7;
+    // GRIM_FLAG_* of skipped reads, the same in every thread, reported once
+    // after the loop: a skip path must not end in a branch on the thread index
+    // (if (t == 0) ... continue), which the compiler may thread across the
+    // loop's back edge so that the other threads re-enter the loop at its
+    // barrier without thread 0 having fetched the next read
+    uint32_t skipped = 0;
     for (;;) {
         if (t == 0)
             next_read = atomicAdd(a.counter, 1u);
@@ -266,13 +273,16 @@ __global__ __launch_bounds__(256) void window_kernel(WindowArgs a)
         __syncthreads();
         if (slot >= a.n_reads)
             break;
-        const uint64_t r = slot;
+        const uint64_t r = a.order ? (uint64_t)a.order[slot] : slot;
+        if (r >= a.n_reads) {  // an order entry naming no read: skipped
+            skipped |= GRIM_FLAG_READ;
+            continue;
+        }
         const uint64_t p0 = a.cand_off[r], p1 = a.cand_off[r + 1];
         if (p1 <= p0)
             continue;
         if (p1 > a.n_pairs) {
-            if (t == 0)
-                atomicOr(a.status, GRIM_FLAG_CAND_OFF);
+            skipped |= GRIM_FLAG_CAND_OFF;
             continue;
         }
         const uint32_t L = a.read_len[r];
@@ -282,8 +292,7 @@ __global__ __launch_bounds__(256) void window_kernel(WindowArgs a)
         if (L > a.max_len || off > nb || L > nb - off) {
             for (uint64_t k = p0 + t; k < p1; k += blockDim.x)
                 a.counts[k] = -1;
-            if (t == 0)
-                atomicOr(a.status, GRIM_FLAG_READ);
+            skipped |= GRIM_FLAG_READ;
             continue;
         }
         const uint32_t ntok = L >= (uint32_t)Q ? L - Q + 1 : 0u;
@@ -433,6 +442,8 @@ __global__ __launch_bounds__(256) void window_kernel(WindowArgs a)
         }
         __syncthreads();  // toks reused by the next read
     }
+    if (t == 0 && skipped)
+        atomicOr(a.status, skipped);
 }
 
 }  // namespace
@@ -481,6 +492,104 @@ hipError_t launch_window(hipStream_t s, int q, uint32_t cus, size_t lds, const W
     if (grid > a.n_reads)
         grid = a.n_reads;
     return hipLaunchKernel(k, dim3((uint32_t)grid), dim3(256), args, lds, s);
+}
+
+// ------------------------------------------------------- processing order
+// A counting sort of the reads by window-start bucket: count, exclusive scan,
+// scatter.  Reads with overlapping windows then run close together in time and
+// share row segments through L2; the filter's outputs do not depend on the
+// order, so the order of reads within a bucket is left to the atomics.
+
+__device__ __forceinline__ uint32_t order_bucket(uint32_t lo, uint64_t n_bins, uint32_t shift,
+                                                 uint32_t n_buckets)
+{
+    return lo < n_bins ? lo >> shift : n_buckets - 1;
+}
+
+__global__ __launch_bounds__(256) void order_count_kernel(const uint32_t *__restrict__ win_lo,
+                                                          uint32_t n, uint64_t n_bins,
+                                                          uint32_t shift, uint32_t n_buckets,
+                                                          uint32_t *cnt)
+{
+    for (uint32_t i = blockIdx.x * 256u + threadIdx.x; i < n; i += gridDim.x * 256u)
+        atomicAdd(&cnt[order_bucket(win_lo[i], n_bins, shift, n_buckets)], 1u);
+}
+
+// Exclusive scan of cnt[0, n) in place by one workgroup of 1024 threads, in
+// chunks of 1024 with a running carry.
+__global__ __launch_bounds__(1024) void order_scan_kernel(uint32_t *cnt, uint32_t n)
+{
+    __shared__ uint32_t wsum[16];
+    const uint32_t t = threadIdx.x, lane = t & 63u, wv = t >> 6;
+    uint32_t carry = 0;
+    for (uint32_t base = 0; base < n; base += 1024u) {
+        const uint32_t i = base + t;
+        const uint32_t v = i < n ? cnt[i] : 0u;
+        uint32_t x = v;  // inclusive scan within the wavefront
+        for (uint32_t d = 1; d < 64; d <<= 1) {
+            const uint32_t y = __shfl_up(x, d, 64);
+            if (lane >= d)
+                x += y;
+        }
+        if (lane == 63)
+            wsum[wv] = x;
+        __syncthreads();
+        if (t < 16) {  // inclusive scan of the 16 wavefront sums
+            uint32_t sw = wsum[t];
+            for (uint32_t d = 1; d < 16; d <<= 1) {
+                const uint32_t y = __shfl_up(sw, d, 64);
+                if (t >= d)
+                    sw += y;
+            }
+            wsum[t] = sw;
+        }
+        __syncthreads();
+        if (i < n)
+            cnt[i] = carry + (wv ? wsum[wv - 1] : 0u) + x - v;
+        carry += wsum[15];
+        __syncthreads();  // wsum is rewritten by the next chunk
+    }
+}
+
+__global__ __launch_bounds__(256) void order_scatter_kernel(const uint32_t *__restrict__ win_lo,
+                                                            uint32_t n, uint64_t n_bins,
+                                                            uint32_t shift, uint32_t n_buckets,
+                                                            uint32_t *cnt, uint32_t *order)
+{
+    for (uint32_t i = blockIdx.x * 256u + threadIdx.x; i < n; i += gridDim.x * 256u) {
+        const uint32_t pos = atomicAdd(&cnt[order_bucket(win_lo[i], n_bins, shift, n_buckets)], 1u);
+        order[pos] = i;
+    }
+}
+
+// Buckets of 1024 bins (a quarter of a 4096-bin window), wider when needed to
+// keep at most 2^16 of them, plus one for starts past the last bin.
+uint32_t order_shift(uint64_t n_bins, uint32_t *n_buckets)
+{
+    uint32_t shift = 10;
+    while (((n_bins ? n_bins - 1 : 0) >> shift) + 2 > 65536u)
+        ++shift;
+    *n_buckets = (uint32_t)(((n_bins ? n_bins - 1 : 0) >> shift) + 2);
+    return shift;
+}
+
+hipError_t launch_window_order(hipStream_t s, uint32_t cus, const uint32_t *win_lo, uint32_t n,
+                               uint64_t n_bins, uint32_t shift, uint32_t n_buckets, uint32_t *cnt,
+                               uint32_t *order)
+{
+    const uint32_t grid = (uint32_t)std::min<uint64_t>((n + 255u) / 256u, (uint64_t)cus * 8u);
+    hipLaunchKernelGGL(order_count_kernel, dim3(grid), dim3(256), 0, s, win_lo, n, n_bins, shift,
+                       n_buckets, cnt);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(order_scan_kernel, dim3(1), dim3(1024), 0, s, cnt, n_buckets);
+    e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(order_scatter_kernel, dim3(grid), dim3(256), 0, s, win_lo, n, n_bins, shift,
+                       n_buckets, cnt, order);
+    return hipGetLastError();
 }
 
 }  // namespace grim

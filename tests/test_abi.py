@@ -85,13 +85,12 @@ def test_pack_bases_layout():
     assert e.value.code == g.GRIM_E_BASE
 
 
-def test_window_order_is_switched_off():
-    """The device-side window order reports GRIM_E_UNSUPPORTED and touches no
+def test_window_order_argument_checks():
+    """The window-order calls refuse a NULL index or output before touching a
     device (callable without a GPU)."""
     import ctypes
     import paper_1711_01177_amd as g
     n = ctypes.c_uint64(77)
-    assert g._lib.grim_window_order_workspace_size(None, 10, ctypes.byref(n)) == \
-        g.GRIM_E_UNSUPPORTED
-    assert n.value == 0
-    assert g._lib.grim_window_order(None, None, 10, None, None, 0, None) == g.GRIM_E_UNSUPPORTED
+    assert g._lib.grim_window_order_workspace_size(None, 10, ctypes.byref(n)) == g.GRIM_E_INVALID
+    assert n.value == 77
+    assert g._lib.grim_window_order(None, None, 10, None, None, 0, None) == g.GRIM_E_INVALID

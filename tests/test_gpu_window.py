@@ -141,9 +141,10 @@ def test_windows_token_blocks_and_many_reads():
     assert_same(out, orc, "token blocks")
 
 
-@pytest.mark.skip(reason="device-side window order switched off: its first GPU run stopped "
-                         "responding with no cause found by reading; the entry points return "
-                         "GRIM_E_UNSUPPORTED until one is shown")
+@pytest.mark.skip(reason="checks the first device-side window order (a library sort: the stable "
+                         "argsort of the window starts), whose first GPU run stopped responding "
+                         "with no cause found; that code is gone, and the bucket order that "
+                         "replaced it is tested by test_window_bucket_order")
 def test_window_order_and_ordered_filter():
     """grim_window_order is the stable argsort of the window starts; filtering in
     that order, or in any other permutation, gives the same outputs as index
@@ -186,3 +187,78 @@ def test_window_order_and_ordered_filter():
     keep = np.ones(c.size, bool)
     keep[p0:p1] = False
     assert np.array_equal(c[keep], orc[0][keep])
+
+
+def test_window_bucket_order():
+    """grim_window_order is a permutation of the reads with their window-start
+    buckets (1024 bins each, starts past the last bin last) non-decreasing;
+    filtering in that order, in a random order or in index order gives the
+    oracle's outputs; an order entry naming no read is skipped and flagged, and
+    the read it replaced keeps the previous contents of its counts."""
+    import torch
+    g = lib()
+    q, B, O = 5, 40, 21
+    ref = gs.reference(81, 1_000_000, 0.3, 30, 300, 0.85, 0.98)
+    nb = (ref.size + B - 1) // B                # 25,000 bins: 25 buckets
+    rng = np.random.default_rng(82)
+    rd = gs.reads(83, ref, 900, [100, 150, 250], [500, 1000])
+    reads = [rd["codes"][int(o):int(o) + int(L)] for o, L in zip(rd["read_off"], rd["read_len"])]
+    n = len(reads)
+    sizes = rng.choice([1, 33, 500, 2048], size=n)
+    win_lo = np.clip(np.minimum(rd["read_z"] // B, nb - 1).astype(np.int64) - sizes // 2, 0, nb - 1)
+    win_lo[:200] = rng.integers(0, 40, size=200)     # one crowded bucket
+    win_lo[200:210] = 7
+    win_lo[210:214] = [nb, nb + 5, nb + 3000, nb + 10_000_000]  # windows past the last bin
+    w = window_workload(ref, q, B, O, reads, rd["read_e"], win_lo, sizes)
+    idx = g.grim_build_bins(ref, q, B, O)
+    idx.transpose()
+    wl = torch.from_numpy(win_lo.astype(np.uint32).view(np.int32)).cuda()
+    bucket = np.where(win_lo < nb, win_lo >> 10, ((nb - 1) >> 10) + 1)
+    for _ in range(2):                          # twice: the bucket counts start from zero
+        order = g.grim_window_order(idx, wl)
+        torch.cuda.synchronize()
+        got = order.cpu().numpy().view(np.uint32)[:n].astype(np.int64)
+        assert np.array_equal(np.sort(got), np.arange(n))
+        assert np.all(np.diff(bucket[got]) >= 0)
+    orc = oracle_run(w)
+    base = run_windows(g, idx, w, win_lo)
+    assert base[2] == g.GRIM_E_BIN_RANGE and orc[2]
+    assert_same(base, orc, "index order")
+    assert_same(run_windows(g, idx, w, win_lo, order="sorted"), orc, "bucket order")
+    assert_same(run_windows(g, idx, w, win_lo, order=rng.permutation(n)), orc, "random order")
+    bad = np.arange(n)
+    bad[5] = n + 3
+    c, b, rc, flags = run_windows(g, idx, w, win_lo, order=bad)
+    assert flags & g.GRIM_FLAG_READ and not base[3] & g.GRIM_FLAG_READ
+    assert rc == g.GRIM_E_BIN_RANGE             # reported before GRIM_E_READ
+    p0, p1 = int(w["cand_off"][5]), int(w["cand_off"][6])
+    assert p1 > p0 and np.all(c[p0:p1] == -9)
+    keep = np.ones(c.size, bool)
+    keep[p0:p1] = False
+    assert np.array_equal(c[keep], orc[0][keep])
+
+
+def test_windows_invalid_reads_skipped():
+    """Reads longer than max_len are skipped with counts -1, no pass bits and
+    GRIM_FLAG_READ, from index order and from a processing order alike; the
+    other reads' outputs are the oracle's."""
+    g = lib()
+    ref = gs.reference(91, 400_000)
+    q, B, O = 5, 200, 105
+    reads = [ref[1000:1300], ref[2000:2150], ref[3000:3100], ref[5000:5400], ref[7000:7180]]
+    win_lo = [3, 10, 20, 1999, 40]
+    sizes = [50, 70, 33, 5, 64]
+    w = window_workload(ref, q, B, O, reads, [500] * 5, win_lo, sizes)
+    idx = g.grim_build_bins(ref, q, B, O)
+    idx.transpose()
+    orc = oracle_run(w)
+    bad = np.zeros(w["cand_off"][-1], bool)
+    for r in (0, 3):                            # 300 and 400 bases, over max_len = 200
+        bad[int(w["cand_off"][r]):int(w["cand_off"][r + 1])] = True
+    for order in (None, [4, 3, 2, 1, 0]):
+        c, b, rc, flags = run_windows(g, idx, w, win_lo, max_len=200, order=order)
+        assert rc == g.GRIM_E_READ and flags & g.GRIM_FLAG_READ
+        assert np.all(c[bad] == -1) and np.array_equal(c[~bad], orc[0][~bad])
+        bits = np.unpackbits(b.view(np.uint8), bitorder="little")[:bad.size].astype(bool)
+        want = np.unpackbits(orc[1].view(np.uint8), bitorder="little")[:bad.size].astype(bool)
+        assert not bits[bad].any() and np.array_equal(bits[~bad], want[~bad])
