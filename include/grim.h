@@ -370,8 +370,9 @@ void grim_seed_index_free(grim_seed_index_t *si);
  * to the first `cap`.  Reads outside the packed buffer, and reads longer than
  * reads->max_len when it is not 0, get no candidates.  Calls on one seed index
  * take turns (the index keeps its device temporaries between calls).
- * Synchronous; allocates the result (CSR offsets n_reads + 1 u64, bins u32) on
- * the device.  GRIM_E_UNSUPPORTED beyond 2^31 - 1 seed hits or reads. */
+ * Synchronous; the result (CSR offsets n_reads + 1 u64, bins u32) is device
+ * memory, a buffer kept from a freed list of this index when one fits, else
+ * allocated.  GRIM_E_UNSUPPORTED beyond 2^31 - 1 seed hits or reads. */
 int grim_seed_candidates(const grim_seed_index_t *si, const grim_batch_t *reads,
                          uint64_t bin_stride, uint32_t cap, grim_candidates_t **out, void *stream);
 
@@ -381,6 +382,10 @@ int grim_candidates_info(const grim_candidates_t *c, uint64_t *n_reads, uint64_t
 /* Copy a candidate list to host memory (cand_off: n_reads + 1, cand_bin: n_pairs). */
 int grim_candidates_copy_to_host(const grim_candidates_t *c, uint64_t *cand_off,
                                  uint32_t *cand_bin);
+/* Free a candidate list: waits for the device's queued work (as hipFree
+ * does), then keeps its buffer for later lists of the same seed index (at most
+ * two buffers per index are kept, until the index and every list made from
+ * it have been freed). */
 void grim_candidates_free(grim_candidates_t *c);
 
 /* ---------------------------------------------------------------- HIP graphs */

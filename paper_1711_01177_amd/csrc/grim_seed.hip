@@ -18,10 +18,72 @@
 
 #include <algorithm>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <new>
+#include <utility>
+#include <vector>
 
 #include "grim_internal.h"
+
+// Result buffers of freed candidate lists, kept for the next lists of the same
+// seed index: a free then costs a device synchronisation (as hipFree's does)
+// instead of unmapping memory, and a call that finds a buffer allocates
+// nothing.  Shared by the index and its lists, so either may go first; at most
+// kCachedBuffers are kept, the rest freed.
+struct SeedBufferCache {
+    static constexpr size_t kCachedBuffers = 2;
+    int device = 0;
+    std::mutex mu;
+    std::vector<std::pair<uint8_t *, uint64_t>> bufs;  // (buffer, bytes)
+
+    // a cached buffer of at least `bytes` bytes and at most twice that (plus
+    // 64 MiB), or null
+    uint8_t *take(uint64_t bytes, uint64_t *got)
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        size_t best = bufs.size();
+        for (size_t i = 0; i < bufs.size(); ++i)
+            if (bufs[i].second >= bytes && bufs[i].second <= 2 * bytes + (64ull << 20) &&
+                (best == bufs.size() || bufs[i].second < bufs[best].second))
+                best = i;
+        if (best == bufs.size())
+            return nullptr;
+        uint8_t *b = bufs[best].first;
+        *got = bufs[best].second;
+        bufs.erase(bufs.begin() + best);
+        return b;
+    }
+    // keep a buffer no queued work uses any more; the smallest one goes when
+    // more than kCachedBuffers are held
+    void give(uint8_t *b, uint64_t bytes)
+    {
+        uint8_t *drop = nullptr;
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            bufs.emplace_back(b, bytes);
+            if (bufs.size() > kCachedBuffers) {
+                size_t small = 0;
+                for (size_t i = 1; i < bufs.size(); ++i)
+                    if (bufs[i].second < bufs[small].second)
+                        small = i;
+                drop = bufs[small].first;
+                bufs.erase(bufs.begin() + small);
+            }
+        }
+        (void)hipFree(drop);
+    }
+    ~SeedBufferCache()
+    {
+        int cur = 0;
+        const bool have = hipGetDevice(&cur) == hipSuccess;
+        (void)hipSetDevice(device);
+        for (auto &b : bufs)
+            (void)hipFree(b.first);
+        if (have)
+            (void)hipSetDevice(cur);
+    }
+};
 
 struct grim_seed_index {
     uint32_t k;
@@ -34,13 +96,16 @@ struct grim_seed_index {
     std::mutex mu;
     uint8_t *tmp[3] = {nullptr, nullptr, nullptr};
     uint64_t tmp_bytes[3] = {0, 0, 0};
+    std::shared_ptr<SeedBufferCache> cache;
 };
 
 struct grim_candidates {
     uint64_t n_reads, n_pairs;
     uint8_t *buf;      // one allocation: the offsets, then the bins
+    uint64_t buf_bytes;
     uint64_t *d_off;   // n_reads + 1
     uint32_t *d_bin;   // n_pairs (at least one element)
+    std::shared_ptr<SeedBufferCache> cache;  // where buf goes when the list is freed
 };
 
 namespace grim {
@@ -107,16 +172,21 @@ __device__ uint64_t block_scan_u64(uint64_t v, uint64_t *lds, uint64_t *total)
     return before + incl - v;
 }
 
+// Per-block totals; loads strided by the block width so that every load
+// instruction reads one contiguous run.
 template <typename T>
 __global__ __launch_bounds__(256) void scan_totals_kernel(const T *__restrict__ in, uint64_t n,
                                                           uint64_t *block_tot)
 {
     __shared__ uint64_t lds[4];
-    const uint64_t i0 = (uint64_t)blockIdx.x * kScanPerBlock + (uint64_t)threadIdx.x * kScanPerThread;
+    const uint64_t b0 = (uint64_t)blockIdx.x * kScanPerBlock;
     uint64_t s = 0;
-    for (int j = 0; j < kScanPerThread; ++j)
-        if (i0 + j < n)
-            s += in[i0 + j];
+#pragma unroll
+    for (int j = 0; j < kScanPerThread; ++j) {
+        const uint64_t i = b0 + (uint64_t)j * 256 + threadIdx.x;
+        if (i < n)
+            s += in[i];
+    }
     uint64_t tot;
     block_scan_u64(s, lds, &tot);
     if (threadIdx.x == 0)
@@ -161,6 +231,8 @@ __global__ __launch_bounds__(1024) void scan_tot_kernel(uint64_t *sums, uint64_t
         *total = carry_s;
 }
 
+// The block's kScanPerBlock inputs go through LDS: loaded and stored with
+// contiguous runs per instruction, scanned as 16 consecutive values per thread.
 template <typename T>
 __global__ __launch_bounds__(256) void scan_apply_kernel(const T *__restrict__ in, uint64_t n,
                                                          const uint64_t *__restrict__ block_base,
@@ -168,20 +240,40 @@ __global__ __launch_bounds__(256) void scan_apply_kernel(const T *__restrict__ i
                                                          uint64_t *__restrict__ out)
 {
     __shared__ uint64_t lds[4];
-    const uint64_t i0 = (uint64_t)blockIdx.x * kScanPerBlock + (uint64_t)threadIdx.x * kScanPerThread;
-    uint64_t s = 0;
-    for (int j = 0; j < kScanPerThread; ++j)
-        if (i0 + j < n)
-            s += in[i0 + j];
-    uint64_t tot;
-    uint64_t run = block_base[blockIdx.x] + block_scan_u64(s, lds, &tot);
+    __shared__ uint64_t vals[kScanPerBlock + kScanPerBlock / 16];  // padded: one word per 16
+    const int t = threadIdx.x;
+    const uint64_t b0 = (uint64_t)blockIdx.x * kScanPerBlock;
+    auto slot = [](uint32_t k) { return k + (k >> 4); };
+#pragma unroll
     for (int j = 0; j < kScanPerThread; ++j) {
-        if (i0 + j < n) {
-            out[i0 + j] = run;
-            run += in[i0 + j];
-        }
+        const uint32_t k = (uint32_t)j * 256u + (uint32_t)t;
+        const uint64_t i = b0 + k;
+        vals[slot(k)] = i < n ? (uint64_t)in[i] : 0ull;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0)
+    __syncthreads();
+    uint64_t v[kScanPerThread];
+    uint64_t sum = 0;
+#pragma unroll
+    for (int j = 0; j < kScanPerThread; ++j) {
+        v[j] = vals[slot((uint32_t)t * kScanPerThread + j)];
+        sum += v[j];
+    }
+    uint64_t tot;
+    uint64_t run = block_base[blockIdx.x] + block_scan_u64(sum, lds, &tot);
+#pragma unroll
+    for (int j = 0; j < kScanPerThread; ++j) {
+        vals[slot((uint32_t)t * kScanPerThread + j)] = run;
+        run += v[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kScanPerThread; ++j) {
+        const uint32_t k = (uint32_t)j * 256u + (uint32_t)t;
+        const uint64_t i = b0 + k;
+        if (i < n)
+            out[i] = vals[slot(k)];
+    }
+    if (blockIdx.x == 0 && t == 0)
         out[n] = *total;
 }
 
@@ -288,31 +380,32 @@ __global__ __launch_bounds__(256) void seed_emit_kernel(
         const uint32_t ns = (uint32_t)min<uint64_t>(kWave, n_items - i0);
         const uint64_t i = i0 + lane;
         const uint64_t first = item_off[i0];
-        const uint64_t excl = (lane < (int)ns ? item_off[i] : item_off[i0 + ns]) - first;
-        const uint64_t a = lane < (int)ns ? item_a[i] : 0u;
-        const uint64_t o = lane < (int)ns ? item_o[i] : 0u;
-        const uint64_t total = item_off[i0 + ns] - first;
+        // offsets within the group fit 32 bits: a call has fewer than 2^31 hits
+        const uint32_t excl = (uint32_t)((lane < (int)ns ? item_off[i] : item_off[i0 + ns]) - first);
+        const uint32_t a = lane < (int)ns ? item_a[i] : 0u;
+        const uint32_t o = lane < (int)ns ? item_o[i] : 0u;
+        const uint32_t total = (uint32_t)(item_off[i0 + ns] - first);
         constexpr int U = 4;
-        for (uint64_t e0 = 0; e0 < total; e0 += (uint64_t)U * kWave) {
+        for (uint32_t e0 = 0; e0 < total; e0 += (uint32_t)U * kWave) {
             uint32_t p[U];
             int64_t po[U];
             bool ok[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const uint64_t e = e0 + (uint64_t)u * kWave + lane;
+                const uint32_t e = e0 + (uint32_t)u * kWave + lane;
                 // the item of hit e: the last item j < ns whose hits start at or before e
                 int pos = 0;
 #pragma unroll
                 for (int step = kWave / 2; step >= 1; step >>= 1) {
                     const int cand = pos + step;
-                    const uint64_t ec = __shfl(excl, cand);
+                    const uint32_t ec = __shfl(excl, cand);
                     if (cand < (int)ns && ec <= e)
                         pos = cand;
                 }
-                const uint64_t ap = __shfl(a, pos), ep = __shfl(excl, pos);
+                const uint32_t ap = __shfl(a, pos), ep = __shfl(excl, pos);
                 po[u] = (int64_t)__shfl(o, pos);
                 ok[u] = e < total;
-                p[u] = ok[u] ? idx_pos[ap + (e - ep)] : 0u;
+                p[u] = ok[u] ? idx_pos[(uint64_t)ap + (e - ep)] : 0u;
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
@@ -322,7 +415,9 @@ __global__ __launch_bounds__(256) void seed_emit_kernel(
                         z = 0;
                     if ((uint64_t)z > G - 1)
                         z = (int64_t)(G - 1);
-                    hb[first + e0 + (uint64_t)u * kWave + lane] = (uint32_t)((uint64_t)z / B);
+                    // z < G < 2^32: a 32-bit division (every bin is 0 for B >= 2^32)
+                    hb[first + e0 + (uint32_t)u * kWave + lane] =
+                        (B >> 32) ? 0u : (uint32_t)z / (uint32_t)B;
                 }
             }
         }
@@ -414,15 +509,108 @@ __device__ __forceinline__ uint64_t unique_keys(Src x, uint64_t m, uint32_t cap,
     return u < cap ? u : cap;
 }
 
+// The same network on R keys per lane (64 R keys, key e = r * 64 + lane in
+// v[r], keys past the read's end +infinity): steps between keys 64 or more
+// apart exchange registers of one lane, the others exchange one register
+// between lanes; the first step of a stage above 64 does both (key e pairs
+// with e ^ (k - 1): lane ^ 63 in register r ^ ((k - 1) >> 6)).
+template <int R>
+__device__ __forceinline__ void sort_regs(uint32_t (&v)[R], int lane)
+{
+    constexpr int P = kWave * R;
+#pragma unroll
+    for (int k = 2; k <= P; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j >= 1; j >>= 1) {
+            const bool flip = j == (k >> 1);
+            if (flip && k > kWave) {
+                const int rm = (k - 1) >> 6;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int r2 = r ^ rm;
+                    if (r < r2) {
+                        const uint32_t t1 = __shfl(v[r2], lane ^ (kWave - 1));
+                        const uint32_t t2 = __shfl(v[r], lane ^ (kWave - 1));
+                        v[r] = min(v[r], t1);
+                        v[r2] = max(v[r2], t2);
+                    }
+                }
+            } else if (j >= kWave) {
+                const int rm = j >> 6;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int r2 = r ^ rm;
+                    if (r < r2) {
+                        const uint32_t a = v[r], b = v[r2];
+                        v[r] = min(a, b);
+                        v[r2] = max(a, b);
+                    }
+                }
+            } else {
+                const int partner = flip ? (lane ^ (k - 1)) : (lane ^ j);
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const uint32_t w = __shfl(v[r], partner);
+                    v[r] = lane < partner ? min(v[r], w) : max(v[r], w);
+                }
+            }
+        }
+    }
+}
+
+// Distinct keys of the sorted registers (key e = r * 64 + lane, m keys), at
+// most cap of them, to out[0 ..); returns how many.  out may hold the keys'
+// source: every key is in registers before the first store.
+template <int R>
+__device__ __forceinline__ uint64_t unique_regs(const uint32_t (&v)[R], uint64_t m, uint32_t cap,
+                                                uint32_t *out, int lane)
+{
+    const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+    uint64_t u = 0;
+    uint32_t carry = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const uint64_t e = (uint64_t)r * kWave + lane;
+        const uint32_t x = v[r];
+        const uint32_t prev = __shfl_up(x, 1);
+        const bool first = e < m && (e == 0 || (lane == 0 ? carry : prev) != x);
+        const uint64_t mk = __ballot(first);
+        const uint64_t pos = u + __popcll(mk & below);
+        carry = __shfl(x, kWave - 1);
+        if (first && pos < cap)
+            out[pos] = x;
+        u += __popcll(mk);
+    }
+    return u < cap ? u : cap;
+}
+
+// One read's 64 < m <= 64 R hits: loaded into registers, sorted, reduced in place.
+template <int R>
+__device__ __forceinline__ uint64_t sort_unique_regs(uint32_t *hits, uint64_t m, uint32_t cap,
+                                                     int lane)
+{
+    uint32_t v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const uint64_t e = (uint64_t)r * kWave + lane;
+        v[r] = e < m ? hits[e] : 0xffffffffu;
+    }
+    sort_regs<R>(v, lane);
+    return unique_regs<R>(v, m, cap, hits, lane);
+}
+
 // Per read: its hit bins hb[hit_off[r] ..+ m) reduced to the distinct ones,
 // ascending, up to the cap, written back in place from hit_off[r]; their number
 // to ucnt[r].  seed_sort_kernel takes kSortReads consecutive reads per
-// wavefront (their hit ranges and short lists loaded together): up to 64 hits
-// sorted in registers, up to kMidCap in the wavefront's LDS; longer reads go
-// to a list that seed_sort_long_kernel works through one workgroup per read,
-// sorting kSortCap hits in LDS and longer lists in place in global memory.
+// wavefront (their hit ranges and short lists loaded together) and sorts each
+// read's hits in registers: one per lane up to 64, else R = 2 .. 8 per lane
+// (up to kMidCap); longer reads go to a list that seed_sort_wide_kernel works
+// through one wavefront per read with 16 or 32 keys per lane (up to kWideCap)
+// and seed_sort_long_kernel one workgroup per read beyond that, sorting
+// kSortCap hits in LDS and longer lists in place in global memory.
 constexpr uint32_t kMidCap = 512;
-constexpr uint32_t kSortCap = 2048;
+constexpr uint32_t kWideCap = 2048;
+constexpr uint32_t kSortCap = 8192;
 constexpr int kSortWaves = 4;
 
 constexpr int kSortReads = 4;  // consecutive reads per wavefront, their loads in flight together
@@ -432,9 +620,7 @@ __global__ __launch_bounds__(kSortWaves * kWave) void seed_sort_kernel(
     uint64_t *__restrict__ ucnt, uint32_t *__restrict__ long_list,
     uint32_t *__restrict__ long_count)
 {
-    __shared__ uint32_t keys_lds[kSortWaves][kMidCap];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    uint32_t *keys = keys_lds[wv];
     const uint64_t r0 = ((uint64_t)blockIdx.x * kSortWaves + wv) * kSortReads;
     if (r0 >= n_reads)
         return;
@@ -463,23 +649,44 @@ __global__ __launch_bounds__(kSortWaves * kWave) void seed_sort_kernel(
             if (lane == 0)
                 long_list[atomicAdd(long_count, 1u)] = (uint32_t)r;
             continue;
+        } else if (m > 128) {
+            u = m > 256 ? sort_unique_regs<8>(hits, m, cap, lane)
+                        : sort_unique_regs<4>(hits, m, cap, lane);
         } else if (m > (uint64_t)kWave) {
-            for (uint64_t i = lane; i < m; i += kWave)
-                keys[i] = hits[i];
-            seed_wave_fence();
-            sort_keys(keys, m, lane, seed_wave_fence);
-            u = unique_keys(keys, m, cap, hits, lane);
+            u = sort_unique_regs<2>(hits, m, cap, lane);
         } else if (m > 0) {
-            keys[lane] = sort_lanes(v[q], lane, (uint32_t)m);
-            seed_wave_fence();
-            u = unique_keys(keys, m, cap, hits, lane);
+            const uint32_t w[1] = {sort_lanes(v[q], lane, (uint32_t)m)};
+            u = unique_regs<1>(w, m, cap, hits, lane);
         }
-        seed_wave_fence();  // keys reused by the next read
         if (lane == 0)
             ucnt[r] = u;
     }
 }
 
+// Reads of the long list with at most kWideCap hits, one wavefront each, 16
+// or 32 keys per lane in registers.
+__global__ __launch_bounds__(256) void seed_sort_wide_kernel(
+    const uint64_t *__restrict__ hit_off, uint32_t cap, uint32_t *__restrict__ hb,
+    uint64_t *__restrict__ ucnt, const uint32_t *__restrict__ long_list,
+    const uint32_t *__restrict__ long_count)
+{
+    const int lane = threadIdx.x & 63;
+    const uint64_t n = *long_count;
+    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+    for (uint64_t j = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); j < n;
+         j += waves) {
+        const uint64_t r = long_list[j];
+        const uint64_t h0 = hit_off[r], m = hit_off[r + 1] - h0;
+        if (m > kWideCap)
+            continue;  // seed_sort_long_kernel's
+        const uint64_t u = m > 1024 ? sort_unique_regs<32>(hb + h0, m, cap, lane)
+                                    : sort_unique_regs<16>(hb + h0, m, cap, lane);
+        if (lane == 0)
+            ucnt[r] = u;
+    }
+}
+
+// Reads of the long list with more than kWideCap hits, one workgroup each.
 __global__ __launch_bounds__(256) void seed_sort_long_kernel(
     const uint64_t *__restrict__ hit_off, uint32_t cap, uint32_t *__restrict__ hb,
     uint64_t *__restrict__ ucnt, const uint32_t *__restrict__ long_list,
@@ -492,6 +699,8 @@ __global__ __launch_bounds__(256) void seed_sort_long_kernel(
         const uint64_t r = long_list[j];
         const uint64_t h0 = hit_off[r], m = hit_off[r + 1] - h0;
         uint32_t *hits = hb + h0;
+        if (m <= kWideCap)
+            continue;  // seed_sort_wide_kernel's
         if (m <= kSortCap) {
             for (uint64_t i = t; i < m; i += blockDim.x)
                 keys[i] = hits[i];
@@ -613,6 +822,12 @@ extern "C" int grim_seed_index_build(const uint32_t *ref_2bit, uint64_t ref_len,
     si->G = ref_len;
     si->d_off = nullptr;
     si->d_pos = nullptr;
+    si->cache = std::shared_ptr<SeedBufferCache>(new (std::nothrow) SeedBufferCache());
+    if (!si->cache) {
+        delete si;
+        return GRIM_E_NOMEM;
+    }
+    si->cache->device = dev;
     if (hipMalloc(&d_ref, nw * 4) != hipSuccess || hipMalloc(&cnt, nk * 4) != hipSuccess ||
         hipMalloc(&btmp, (scan_blocks(nk) + 1) * 8) != hipSuccess ||
         hipMalloc(&si->d_off, (nk + 1) * 8) != hipSuccess ||
@@ -788,12 +1003,20 @@ extern "C" int grim_seed_candidates(const grim_seed_index_t *csi, const grim_bat
     // every hit's bin, then the per-read lists in place; the result (offsets
     // and bins in one allocation) is no longer than the hits together
     hb = reinterpret_cast<uint32_t *>(seed_tmp(si, 2, (total_hits + 1) * 4));
-    if (!hb || hipMalloc(&c->buf, align_up((n + 1) * 8, 256) + (total_hits + 1) * 4) !=
-                   hipSuccess) {
-        c->buf = nullptr;
+    {
+        const uint64_t need = align_up((n + 1) * 8, 256) + (total_hits + 1) * 4;
+        c->buf = si->cache->take(need, &c->buf_bytes);
+        if (!c->buf) {
+            c->buf_bytes = align_up(need, 2ull << 20);
+            if (hipMalloc(&c->buf, c->buf_bytes) != hipSuccess)
+                c->buf = nullptr;
+        }
+    }
+    if (!hb || !c->buf) {
         rc = GRIM_E_NOMEM;
         goto done;
     }
+    c->cache = si->cache;
     c->d_off = reinterpret_cast<uint64_t *>(c->buf);
     c->d_bin = reinterpret_cast<uint32_t *>(c->buf + align_up((n + 1) * 8, 256));
     if (n) {
@@ -809,6 +1032,9 @@ extern "C" int grim_seed_candidates(const grim_seed_index_t *csi, const grim_bat
         SEED_TRY(hipGetLastError());
     }
     if (n) {
+        hipLaunchKernelGGL(seed_sort_wide_kernel, dim3(grid_for((uint64_t)256 * 8 * 256, dev)),
+                           dim3(256), 0, s, hit_off, cap, hb, ucnt, long_list, long_count);
+        SEED_TRY(hipGetLastError());
         hipLaunchKernelGGL(seed_sort_long_kernel, dim3(grid_for((uint64_t)256 * 8 * 256, dev)),
                            dim3(256), 0, s, hit_off, cap, hb, ucnt, long_list, long_count);
         SEED_TRY(hipGetLastError());
@@ -866,6 +1092,11 @@ extern "C" void grim_candidates_free(grim_candidates_t *c)
 {
     if (!c)
         return;
-    (void)hipFree(c->buf);
+    if (c->buf) {
+        if (c->cache && hipDeviceSynchronize() == hipSuccess)
+            c->cache->give(c->buf, c->buf_bytes);
+        else
+            (void)hipFree(c->buf);
+    }
     delete c;
 }

@@ -55,22 +55,27 @@ def test_seeded_mid_workload_filters_like_oracle():
 def test_seed_candidates_hit_count_edges():
     """Hit lists of every size class: a poly-A stretch makes the all-A seed hit
     tens of thousands of times (a list sorted in global memory), reads with
-    exactly 64 / 65 hits (registers / LDS) and 2048 / 2049 hits (LDS / global),
-    and reads without any hit; every list against the oracle."""
+    hit counts on both sides of every class boundary (64 one per lane, 128 /
+    256 / 512 two to eight per lane, 1024 / 2048 sixteen or thirty-two per lane
+    in one wavefront, 8192 in a workgroup's LDS, beyond in global memory), and
+    reads without any hit; every list against the oracle."""
     g = lib()
     k, B = 12, 100
-    ref = gs.reference(23, 400_000)
+    ref = gs.reference(23, 1_400_000)
     ref[100_000:130_000] = 0                      # 30,000 A: the all-A 12-mer hits 29,989 times
     reads = [np.zeros(100, np.uint8), np.zeros(24, np.uint8), ref[5_000:5_100].copy(),
-             np.full(30, 3, np.uint8), ref[200_000:200_011].copy()]
+             np.full(30, 3, np.uint8), ref[60_000:60_011].copy()]
     # reads made of copies of one 12-mer planted n times in the reference
     rng = np.random.default_rng(3)
-    for i, n_copies in enumerate((64, 65, 2048, 2049)):
+    p_next = 140_000
+    for n_copies in (64, 65, 128, 129, 256, 257, 512, 513, 1024, 1025, 2048, 2049, 8192, 8193):
         kmer = rng.integers(0, 4, 12).astype(np.uint8)
         kmer[0] = 1                               # not the all-A k-mer
-        for p0 in range(140_000 + 60_000 * i, 140_000 + 60_000 * i + 13 * n_copies, 13):
+        for p0 in range(p_next, p_next + 13 * n_copies, 13):
             ref[p0:p0 + 12] = kmer
+        p_next += 13 * n_copies + 1000
         reads.append(np.concatenate([kmer, np.full(3, 2, np.uint8)]))
+    assert p_next < ref.size
     codes = np.concatenate(reads)
     lens = np.array([len(r) for r in reads], np.uint32)
     offs = np.zeros(len(reads), np.uint64)
@@ -113,3 +118,38 @@ def test_seed_candidates_item_layouts():
     long_reads = rd["read_len"] > 120
     assert np.all(cnt[long_reads] == 0)
     assert np.array_equal(cnt[~long_reads], w_cnt[~long_reads])
+
+
+def test_seed_candidate_buffers_kept_and_reused():
+    """Freed lists' buffers serve the next lists of the same seed index: lists
+    made after a free (larger, equal and smaller batches) equal the oracle's,
+    and a list that outlives its seed index stays readable until it is freed."""
+    g = lib()
+    k, B = 12, 200
+    ref = gs.reference(41, 1_000_000, 0.2, 20, 300, 0.85, 0.98)
+    rd = gs.reads(42, ref, 20_000, [100, 150], [500])
+
+    def batch(n):
+        o_end = int(rd["read_off"][n - 1]) + int(rd["read_len"][n - 1])
+        return (rd["codes"][:o_end], rd["read_off"][:n], rd["read_len"][:n],
+                g.Batch(rd["codes"][:o_end], rd["read_off"][:n], rd["read_len"][:n],
+                        np.zeros(n, np.uint32), gs.E_DEN, np.zeros(n + 1, np.uint64),
+                        np.zeros(0, np.uint32)))
+
+    si = g.SeedIndex(ref, k)
+    kept = []
+    for n in (20_000, 20_000, 5_000, 20_000, 700, 12_000):
+        codes, offs, lens, b = batch(n)
+        c = g.grim_seed_candidates(si, b, B, 4096)
+        off, bins = c.to_host()
+        w_off, w_bins = oracle.seed_candidates(ref, k, codes, offs, lens, B, 4096)
+        assert np.array_equal(off, w_off) and np.array_equal(bins, w_bins), n
+        if n == 700:
+            kept.append((c, w_off, w_bins))   # lives past the index
+        else:
+            c.free()
+    si.free()
+    c, w_off, w_bins = kept[0]
+    off, bins = c.to_host()
+    assert np.array_equal(off, w_off) and np.array_equal(bins, w_bins)
+    c.free()
