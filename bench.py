@@ -850,13 +850,13 @@ def main():
                                   expect=expect)
             del expect
             # the link ceiling: both directions at once, the busier one decides
-            bpp = serving["link_bytes_per_pair"]
-            ceiling = link["both_each_gbs"] * 1e9 / max(bpp["up"], bpp["down"])
+            link_bpp = serving["link_bytes_per_pair"]
+            ceiling = link["both_each_gbs"] * 1e9 / max(link_bpp["up"], link_bpp["down"])
             serving["link"] = dict(link, ceiling_pairs_per_s=ceiling,
                                    capacity_frac_of_ceiling=serving["capacity_pairs_per_s"] / ceiling)
             log(f"[bench] host link: {link['h2d_gbs']:.1f} GB/s up, {link['d2h_gbs']:.1f} down, "
                 f"{link['both_each_gbs']:.1f} each way at once -> serving ceiling {ceiling:.3e} "
-                f"pairs/s ({bpp['up']:.2f} B up, {bpp['down']:.2f} B down per pair)")
+                f"pairs/s ({link_bpp['up']:.2f} B up, {link_bpp['down']:.2f} B down per pair)")
             serving["copying_submission"] = serving_leg(g, idx, w, rng, loads=(0.5,),
                                                         n_requests=args.serve_requests,
                                                         inplace=False)
