@@ -295,8 +295,7 @@ struct CopyOp {
 struct Slot {
     grim_server *srv = nullptr;
     void *stream = nullptr;        // shared with ticks_per_stream - 1 other slots
-    uint8_t *stage = nullptr;      // pinned staging buffer, mirrors the tick layout
-    uint64_t stage_bytes = 0;
+    uint8_t *stage = nullptr;      // pinned, stage_bytes long, mirrors the tick layout
     // guarded by the server lock; the tick fields below are written by the
     // admission thread while busy is false and belong to the worker from the
     // hand-off until it clears busy
@@ -304,7 +303,6 @@ struct Slot {
     std::vector<Part> parts;
     Layout lay;
     uint64_t dev_off = 0;
-    uint64_t tick = 0;
     uint32_t e_den = 0;
     double turn_wait_s = 0;        // the last launch's wait for its upload turn
     // hand-off between the admission thread, the completion notice and the
@@ -350,8 +348,8 @@ struct grim_server {
     bool stop = false;
     std::thread thr;
 
-    // doorbell: rung by submissions, completion notices and shutdown; the
-    // scheduler sleeps until it changes (bell_mu is never held while taking mu)
+    // doorbell: rung by submissions, retired ticks and shutdown; the admission
+    // thread sleeps until it changes (bell_mu is never held while taking mu)
     std::mutex bell_mu;
     std::condition_variable bell_cv;
     uint64_t bell = 0;
@@ -755,7 +753,6 @@ bool grim_server::admit_tick()
     slot->parts = std::move(take);
     slot->lay = lay;
     slot->dev_off = off;
-    slot->tick = tick;
     slot->e_den = e_den;
     {
         std::lock_guard<std::mutex> lk(slot->m);
@@ -1102,7 +1099,6 @@ extern "C" int grim_serve_create(const grim_index_t *idx, const grim_serve_cfg_t
             free_server_parts(s.get());
             return GRIM_E_NOMEM;
         }
-        sl->stage_bytes = s->stage_bytes;
     }
     grim_server *raw = s.release();
     for (auto &sl : raw->slots) {
