@@ -357,3 +357,35 @@ def test_cancel_request_running_in_parts(setup):
     s = srv.stats()
     assert s["cancelled"] == 1 and s["completed"] == 1
     srv.destroy()
+
+
+@pytest.mark.parametrize("ticks_per_stream,bits_only", [(1, False), (2, False), (3, True), (0, True)])
+def test_scheduling_policies_match_oracle(setup, ticks_per_stream, bits_only):
+    """One request mix through every scheduling policy: one to three ticks per
+    stream, with upload turns (counts and pass bits) and without (pass bits
+    only), ticks small enough that requests run in parts; every request's
+    results against the oracle."""
+    g, w, idx = setup
+    reqs = make_requests(g, w, 40, 17 + ticks_per_stream, max_reads=3000)
+    srv = g.Server(idx, hbm_budget_bytes=128 << 20, max_inflight=32, n_streams=3,
+                   max_tick_pairs=50_000, max_len=256, pass_bits_only=bits_only,
+                   ticks_per_stream=ticks_per_stream)
+    try:
+        tickets = [srv.submit(hb) for _, hb in reqs]
+        for i, ((sub, hb), t) in enumerate(zip(reqs, tickets)):
+            rc, c, b, st = srv.wait(t)
+            assert rc == 0, (i, rc)
+            if bits_only:
+                passed = oracle.filter_batch(w["oidx"], w["q"], sub["codes"], sub["read_off"],
+                                             sub["read_len"], sub["read_e"], sub["e_den"],
+                                             sub["cand_off"], sub["cand_bin"],
+                                             n_threads=gs.default_threads())[1]
+                assert c is None
+                assert np.array_equal(b, oracle.pack_bitmask(passed)), i
+            else:
+                assert oracle_check(w, sub, c, b), f"request {i} differs from the oracle"
+        stats = srv.stats()
+        assert stats["completed"] == len(reqs) and stats["failed"] == 0
+        assert stats["ticks"] > len(reqs) // 2
+    finally:
+        srv.destroy()
