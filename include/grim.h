@@ -430,6 +430,19 @@ typedef struct grim_server grim_server_t;
  * copies its counts back to find it. */
 #define GRIM_SERVE_PASS_BITS_ONLY 1u
 
+/* Server options: how results come back to host memory.  By default the
+ * server probes its streams at creation; when they all share one copy engine
+ * (so that an upload and a download cannot overlap) and results include
+ * counts, a small kernel stores the results straight into the page-locked host
+ * buffers instead of a copy-engine download, and otherwise the copy engine
+ * moves them.  These flags fix the choice: GRIM_SERVE_STORE_DOWNLOADS always
+ * stores from the kernel (except into pageable in-place result buffers, which
+ * the device cannot write: those still come back by the copy engine),
+ * GRIM_SERVE_ENGINE_DOWNLOADS always uses the copy engine.  Setting both is
+ * GRIM_E_INVALID.  Results are the same bytes either way. */
+#define GRIM_SERVE_STORE_DOWNLOADS 2u
+#define GRIM_SERVE_ENGINE_DOWNLOADS 4u
+
 typedef struct grim_serve_cfg {
     uint64_t hbm_budget_bytes;  /* device bytes for request buffers (0 = 1 GiB)     */
     uint32_t max_inflight;      /* requests on the device at once (0 = 1024)        */
@@ -465,6 +478,7 @@ typedef struct grim_serve_stats {
                                  waits for upload turns excluded)                     */
     double sched_retire_s;    /* worker time handing results back (all workers)         */
     double sched_admit_s;     /* admission thread time forming ticks                    */
+    uint32_t stream_groups;   /* copy-engine groups the streams were split between (1, 2) */
 } grim_serve_stats_t;
 
 /* Create a server on the current device.  It allocates its device pool

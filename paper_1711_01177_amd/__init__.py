@@ -48,6 +48,8 @@ GRIM_NOALLOC_SCRATCH_BYTES = 16 << 20
 GRIM_FLAG_BIN_RANGE = 1
 GRIM_FLAG_READ = 2
 GRIM_SERVE_PASS_BITS_ONLY = 1
+GRIM_SERVE_STORE_DOWNLOADS = 2
+GRIM_SERVE_ENGINE_DOWNLOADS = 4
 GRIM_FLAG_CAND_OFF = 4
 
 _u8p = ctypes.POINTER(ctypes.c_uint8)
@@ -106,7 +108,8 @@ class grim_serve_stats_t(ctypes.Structure):
                 ("max_ms", ctypes.c_double), ("busy_s", ctypes.c_double),
                 ("pairs_per_s", ctypes.c_double), ("peak_device_bytes", _u64),
                 ("mean_requests_per_tick", ctypes.c_double), ("sched_launch_s", ctypes.c_double),
-                ("sched_retire_s", ctypes.c_double), ("sched_admit_s", ctypes.c_double)]
+                ("sched_retire_s", ctypes.c_double), ("sched_admit_s", ctypes.c_double),
+                ("stream_groups", _u32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -704,15 +707,24 @@ class HostBatch:
 
 
 class Server:
-    """Continuous-batching server over a resident index (owns a grim_server_t)."""
+    """Continuous-batching server over a resident index (owns a grim_server_t).
+
+    downloads: "auto" (the server's choice after probing its streams), "store"
+    (GRIM_SERVE_STORE_DOWNLOADS) or "engine" (GRIM_SERVE_ENGINE_DOWNLOADS)."""
+
+    _DOWNLOADS = {"auto": 0, "store": GRIM_SERVE_STORE_DOWNLOADS,
+                  "engine": GRIM_SERVE_ENGINE_DOWNLOADS}
 
     def __init__(self, index, hbm_budget_bytes=0, max_inflight=0, n_streams=0, max_tick_pairs=0,
-                 max_len=0, pass_bits_only=False, ticks_per_stream=0):
+                 max_len=0, pass_bits_only=False, ticks_per_stream=0, downloads="auto"):
         self.index = index
         self.pass_bits_only = bool(pass_bits_only)
+        if downloads not in self._DOWNLOADS:
+            raise ValueError(f"downloads must be one of {sorted(self._DOWNLOADS)}")
         cfg = grim_serve_cfg_t(int(hbm_budget_bytes), int(max_inflight), int(n_streams),
                                int(max_tick_pairs), int(max_len),
-                               GRIM_SERVE_PASS_BITS_ONLY if pass_bits_only else 0,
+                               (GRIM_SERVE_PASS_BITS_ONLY if pass_bits_only else 0) |
+                               self._DOWNLOADS[downloads],
                                int(ticks_per_stream))
         self._h = ctypes.c_void_p()
         _check(_lib.grim_serve_create(index.handle, ctypes.byref(cfg), ctypes.byref(self._h)),

@@ -19,8 +19,8 @@ LIB = os.path.join(HERE, "libgrim.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["grim_kernels.hip", "grim_checker.hip", "grim_seed.hip", "grim_window.hip",
-           "grim_build.hip", "grim_probe.hip", "grim_api.hip", "grim_host.cpp", "grim_serve.cpp",
-           "grim_serve_hip.cpp"]
+           "grim_build.hip", "grim_probe.hip", "grim_copy.hip", "grim_api.hip", "grim_host.cpp",
+           "grim_serve.cpp", "grim_serve_hip.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",
           f"-I{INCLUDE}", f"-I{CSRC}"]

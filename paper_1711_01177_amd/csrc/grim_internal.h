@@ -129,6 +129,9 @@ hipError_t launch_probe_stream(hipStream_t s, uint32_t grid, const void *src, ui
                                uint32_t *sink);
 hipError_t launch_filter(const void *kernel, dim3 grid, dim3 block, size_t lds_bytes,
                          hipStream_t s, const FilterArgs &a);
+// Device-to-host copy by a kernel storing into page-locked host memory (dst
+// must be memory the device can write; grim_copy.hip).
+hipError_t launch_copy_to_host(hipStream_t s, void *dst, const void *src, uint64_t bytes);
 
 }  // namespace grim
 

@@ -34,6 +34,12 @@
 //   - pass bits only (the upload direction alone loaded): no turns, and two
 //     slots per stream by default, so that a stream's next tick is queued
 //     behind its current one while the host retires the tick before.
+// Uploads and downloads overlap only on streams served by different copy
+// engines, which the runtime assigns out of the server's control: at create the
+// server times candidate streams, keeps streams of both engines when it finds
+// two and puts consecutive ticks on alternate engines; when every candidate
+// shares one engine, downloads of counts go by a kernel storing into the
+// page-locked host memory instead (grim_copy.hip), which needs no engine.
 //
 // A request with more pairs than a tick has room for is admitted in parts, cut
 // at read boundaries; its parts run as separate ticks on the free streams, so
@@ -192,6 +198,7 @@ struct Request {
     uint8_t *host = nullptr;       // block with inputs and results (null when in place)
     bool pinned = false;           // block lives in the server's pinned arena
     bool in_place = false;         // caller-owned arrays used directly
+    bool counts_writable = false;  // the device can store into the result counts directly
     uint64_t arena_off = 0;
     ReqLayout lay{};
     uint64_t n_words = 0, n_reads = 0, n_pairs = 0;
@@ -285,16 +292,18 @@ struct Part {
     bool counts_direct = false;    // counts came back by direct DMA
 };
 
-// One host <-> device copy of a tick.
+// One host <-> device copy of a tick (a download by host stores when `store`).
 struct CopyOp {
     void *dst;
     const void *src;
     uint64_t bytes;
+    bool store = false;
 };
 
 struct Slot {
     grim_server *srv = nullptr;
     void *stream = nullptr;        // shared with ticks_per_stream - 1 other slots
+    int group = 0;                 // the stream's copy-engine group (0 or 1)
     uint8_t *stage = nullptr;      // pinned, stage_bytes long, mirrors the tick layout
     // guarded by the server lock; the tick fields below are written by the
     // admission thread while busy is false and belong to the worker from the
@@ -330,6 +339,10 @@ struct grim_server {
     std::vector<std::unique_ptr<Slot>> slots;
     uint64_t stage_bytes = 0;          // each slot's staging buffer: the largest tick layout
     std::vector<void *> streams;       // slot i queues its ticks on streams[i % n_streams]
+    std::vector<int> stream_group;     // copy-engine group of each stream (0 or 1)
+    uint32_t n_groups = 1;             // 2 when the streams were split between two groups
+    bool store_downloads = false;      // one group: downloads by host stores, not the copy engine
+    int last_group = 1;                // group of the last tick admitted
     // upload turns (taken when results include counts): ticks queue their
     // input copies one at a time, in the order they reach the gate; a turn ends
     // when the tick's inputs are on the device
@@ -614,12 +627,13 @@ void grim_server::retire(Slot &s, double t_launch)
 // false if nothing could be admitted.  Admission thread, mu held.
 bool grim_server::admit_tick()
 {
+    // a free slot, on a stream of the other copy-engine group than the last
+    // tick's when there is one, so that consecutive ticks' uploads and
+    // downloads can run at once
     Slot *slot = nullptr;
-    for (auto &s : slots)
-        if (!s->busy) {
-            slot = s.get();
-            break;
-        }
+    for (auto &sp : slots)
+        if (!sp->busy && (!slot || (slot->group == last_group && sp->group != last_group)))
+            slot = sp.get();
     if (!slot || queue.empty())
         return false;
     // admission: requests in arrival order with the e_den of the first one
@@ -749,6 +763,7 @@ bool grim_server::admit_tick()
         busy_since = now;
     ++ticks;
     reqs_in_ticks += take.size();
+    last_group = slot->group;
     slot->busy = true;
     slot->parts = std::move(take);
     slot->lay = lay;
@@ -773,23 +788,25 @@ namespace {
 struct RunCopier {
     uint8_t *dev, *stage;
     bool h2d;
+    bool store = false;  // downloads by host stores where the destination allows
     std::vector<CopyOp> ops;
     uint64_t run_lo = 0, run_hi = 0;
     bool run = false;
 
-    RunCopier(uint8_t *dev_, uint8_t *stage_, bool h2d_) : dev(dev_), stage(stage_), h2d(h2d_) {}
+    RunCopier(uint8_t *dev_, uint8_t *stage_, bool h2d_, bool store_ = false)
+        : dev(dev_), stage(stage_), h2d(h2d_), store(store_) {}
 
-    void add(uint64_t off, uint8_t *host, uint64_t bytes)
+    void add(uint64_t off, uint8_t *host, uint64_t bytes, bool writable = true)
     {
         if (h2d)
-            ops.push_back({dev + off, host, bytes});
+            ops.push_back({dev + off, host, bytes, false});
         else
-            ops.push_back({host, dev + off, bytes});
+            ops.push_back({host, dev + off, bytes, store && writable});
     }
     void flush()
     {
         if (run)
-            add(run_lo, stage + run_lo, run_hi - run_lo);
+            add(run_lo, stage + run_lo, run_hi - run_lo);  // the stage is page-locked
         run = false;
     }
     // [off, off + bytes) of the stage holds the slice (to device) or receives it
@@ -807,10 +824,10 @@ struct RunCopier {
         run_hi = off + bytes;
     }
     // the slice at off moves straight between `host` and the device
-    void direct(uint64_t off, void *host, uint64_t bytes)
+    void direct(uint64_t off, void *host, uint64_t bytes, bool writable = true)
     {
         flush();
-        add(off, static_cast<uint8_t *>(host), bytes);
+        add(off, static_cast<uint8_t *>(host), bytes, writable);
     }
     // a host slice to the device: by DMA when large, else through the stage
     void put(uint64_t off, const void *src, uint64_t bytes)
@@ -823,11 +840,15 @@ struct RunCopier {
         }
     }
     // queue the planned copies on stream s
-    int issue(void *s) const
+    int issue(void *s) const { return issue(s, 0, ops.size()); }
+    // queue the planned copies [i0, i1) on stream s
+    int issue(void *s, size_t i0, size_t i1) const
     {
-        for (const CopyOp &op : ops) {
-            const int e = h2d ? backend().copy_h2d(op.dst, op.src, op.bytes, s)
-                              : backend().copy_d2h(op.dst, op.src, op.bytes, s);
+        for (size_t i = i0; i < i1; ++i) {
+            const CopyOp &op = ops[i];
+            const int e = h2d        ? backend().copy_h2d(op.dst, op.src, op.bytes, s)
+                          : op.store ? backend().store_d2h(op.dst, op.src, op.bytes, s)
+                                     : backend().copy_d2h(op.dst, op.src, op.bytes, s);
             if (e != GRIM_OK)
                 return GRIM_E_HIP;
         }
@@ -888,10 +909,21 @@ int grim_server::launch(Slot &s)
     for (const Part &pt : s.parts)
         in.put(lay.cand_bin + pt.fused_base * 4, pt.r->cand_bin() + pt.pa, (pt.pb - pt.pa) * 4);
     in.flush();
-    // with upload turns: wait for this tick's turn, queue the input copies,
-    // then the notice that ends the turn once they have run (or end it here if
-    // that notice could not be queued)
+    // with upload turns: wait for this tick's turn, queue the input copies and
+    // the notice that ends the turn once they have run (or end it here if that
+    // notice could not be queued).  When the last copy carries an eighth of the
+    // tick's bytes or more, the notice goes before it, so that the next tick's
+    // uploads are queued while it runs and the link does not idle through the
+    // notice's latency.
     s.turn_wait_s = 0;
+    size_t split = in.ops.size();
+    if (upload_turns && split > 1) {
+        uint64_t total = 0;
+        for (const CopyOp &op : in.ops)
+            total += op.bytes;
+        if (in.ops.back().bytes * 8 >= total)
+            split = in.ops.size() - 1;
+    }
     if (upload_turns) {
         const auto t0 = Clock::now();
         std::unique_lock<std::mutex> lk(up_mu);
@@ -899,7 +931,7 @@ int grim_server::launch(Slot &s)
         up_cv.wait(lk, [&] { return up_turn == mine; });
         s.turn_wait_s = secs(Clock::now() - t0);
     }
-    int rc = in.issue(st);
+    int rc = in.issue(st, 0, split);
     if (upload_turns) {
         if (rc == GRIM_OK && be.notify(st, on_upload_done, &s) != GRIM_OK)
             rc = GRIM_E_HIP;
@@ -908,6 +940,8 @@ int grim_server::launch(Slot &s)
             upload_turn_end();
         }
     }
+    if (rc == GRIM_OK && split < in.ops.size())
+        rc = in.issue(st, split, in.ops.size());
     grim_batch_t b;
     b.reads_2bit = reinterpret_cast<const uint32_t *>(d + lay.words);
     b.n_read_words = std::max<uint64_t>(wbase, 1);  // the layout holds one word more
@@ -932,12 +966,12 @@ int grim_server::launch(Slot &s)
     // results; then the completion notice
     if (rc == GRIM_OK) {
         const bool bits_only = (cfg.flags & GRIM_SERVE_PASS_BITS_ONLY) != 0;
-        RunCopier out{dout, hout, false};
+        RunCopier out{dout, hout, false, store_downloads};
         for (size_t j = 0; j < s.parts.size() && !bits_only; ++j) {
             Part &pt = s.parts[j];
             const uint64_t lo = lay.counts + pt.fused_base * 4, nb = (pt.pb - pt.pa) * 4;
             if (nb >= kDirectBytes) {
-                out.direct(lo, pt.r->counts() + pt.pa, nb);
+                out.direct(lo, pt.r->counts() + pt.pa, nb, pt.r->counts_writable);
                 pt.counts_direct = true;
             } else {
                 out.staged(lo, nb);
@@ -1016,6 +1050,84 @@ void grim_server::run()
 
 namespace {
 
+// The server's n streams.  Copies queued on streams that the runtime serves
+// with one copy engine take turns, even in opposite directions, and which
+// streams share an engine depends on the process's history (on MI355X:
+// measured both as groups of four consecutively created streams, and as one
+// stream of a newly created batch alone against all the others).  An upload
+// overlaps a download (48 GB/s each way instead of 28.5 in turns) only across
+// engines.  So candidate streams are created and timed: an upload on the first
+// candidate with a download on the same stream (in turns by definition), then
+// with a download on each other candidate; those that overlap form the other
+// group.  The chosen streams alternate between the groups (as far as each has
+// streams) and the others are destroyed.  Copies of `bytes` between dev and
+// host (2 * bytes each).  Returns the number of groups found (1 or 2), or 0 if
+// a stream could not be created.
+uint32_t pick_streams(uint32_t n, uint8_t *dev, uint8_t *host, uint64_t bytes,
+                      std::vector<void *> *out, std::vector<int> *group)
+{
+    const grim_serve::Backend &be = backend();
+    const uint32_t n_cand = n > 1 && bytes ? std::max<uint32_t>(8, 2 * n) : n;
+    std::vector<void *> cand;
+    for (uint32_t i = 0; i < n_cand; ++i) {
+        void *st = nullptr;
+        if (be.stream_create(&st) != GRIM_OK) {
+            for (void *c : cand)
+                be.stream_destroy(c);
+            return 0;
+        }
+        cand.push_back(st);
+    }
+    // best of two timings of an upload on the first candidate with a download
+    // on candidate i (0 when a call failed)
+    auto timed = [&](uint32_t i) {
+        double best = 0;
+        for (int rep = 0; rep < 2; ++rep) {
+            const auto t0 = Clock::now();
+            const int e1 = be.copy_h2d(dev, host, bytes, cand[0]);
+            const int e2 = be.copy_d2h(host + bytes, dev + bytes, bytes, cand[i]);
+            const int e3 = be.stream_sync(cand[0]);
+            const int e4 = i ? be.stream_sync(cand[i]) : GRIM_OK;
+            const double dt = secs(Clock::now() - t0);
+            if (e1 || e2 || e3 || e4)
+                return 0.0;
+            best = rep == 0 ? dt : std::min(best, dt);
+        }
+        return best;
+    };
+    std::vector<int> cg(n_cand, 0);
+    uint32_t groups = 1;
+    if (n_cand > n) {
+        (void)timed(0);  // warm-up
+        const double serial = timed(0);
+        for (uint32_t i = 1; i < n_cand && serial > 0; ++i) {
+            const double t = timed(i);
+            if (t > 0 && t < 0.8 * serial) {
+                cg[i] = 1;
+                groups = 2;
+            }
+        }
+    }
+    std::vector<bool> used(n_cand, false);
+    for (uint32_t k = 0; k < n; ++k) {
+        const int want = (int)(k % 2) % (int)groups;
+        uint32_t pick = n_cand;
+        for (uint32_t i = 0; i < n_cand && pick == n_cand; ++i)
+            if (!used[i] && cg[i] == want)
+                pick = i;
+        for (uint32_t i = 0; i < n_cand && pick == n_cand; ++i)
+            if (!used[i])
+                pick = i;
+        used[pick] = true;
+        out->push_back(cand[pick]);
+        group->push_back(cg[pick]);
+    }
+    for (uint32_t i = 0; i < n_cand; ++i)
+        if (!used[i])
+            be.stream_destroy(cand[i]);
+    return groups;
+}
+
 // Frees what grim_serve_create has set up so far (no thread started yet).
 void free_server_parts(grim_server *s)
 {
@@ -1049,8 +1161,9 @@ extern "C" int grim_serve_create(const grim_index_t *idx, const grim_serve_cfg_t
     const bool bits_only = (c.flags & GRIM_SERVE_PASS_BITS_ONLY) != 0;
     if (!c.ticks_per_stream)
         c.ticks_per_stream = bits_only ? 2 : 1;
+    const uint32_t dl_flags = GRIM_SERVE_STORE_DOWNLOADS | GRIM_SERVE_ENGINE_DOWNLOADS;
     if (c.max_len > GRIM_MAX_READ_LEN || c.n_streams > 16 || c.ticks_per_stream > 4 ||
-        (c.flags & ~GRIM_SERVE_PASS_BITS_ONLY))
+        (c.flags & ~(GRIM_SERVE_PASS_BITS_ONLY | dl_flags)) || (c.flags & dl_flags) == dl_flags)
         return GRIM_E_INVALID;
     const grim_serve::Backend &be = backend();
     int dev = 0;
@@ -1080,26 +1193,37 @@ extern "C" int grim_serve_create(const grim_index_t *idx, const grim_serve_cfg_t
     const uint64_t R = std::max<uint64_t>(4096, P / 32);
     const uint64_t W = R * (c.max_len / 16 + 2) + 1;
     s->stage_bytes = std::min<uint64_t>(c.hbm_budget_bytes, plan(W, R, P, ws_need(idx, P)).total);
-    for (uint32_t i = 0; i < c.n_streams; ++i) {
-        void *st = nullptr;
-        if (be.stream_create(&st) != GRIM_OK) {
-            free_server_parts(s.get());
-            return GRIM_E_HIP;
-        }
-        s->streams.push_back(st);
-    }
     s->slots.resize((size_t)c.ticks_per_stream * c.n_streams);
-    for (size_t i = 0; i < s->slots.size(); ++i) {
-        auto &sl = s->slots[i];
+    for (auto &sl : s->slots) {
         sl = std::make_unique<Slot>();
         sl->srv = s.get();
-        sl->stream = s->streams[i % c.n_streams];
         if (be.pinned_alloc(s->stage_bytes, &sl->stage) != GRIM_OK) {
             sl->stage = nullptr;
             free_server_parts(s.get());
             return GRIM_E_NOMEM;
         }
     }
+    // the streams, split between copy-engine groups (probed with the pool and
+    // the first slot's stage, both still unused)
+    const uint64_t probe = std::min<uint64_t>(16ull << 20, std::min(s->stage_bytes, c.hbm_budget_bytes) / 2) & ~255ull;
+    s->n_groups = pick_streams(c.n_streams, s->pool_base, s->slots[0]->stage, probe, &s->streams,
+                               &s->stream_group);
+    if (!s->n_groups) {
+        free_server_parts(s.get());
+        return GRIM_E_HIP;
+    }
+    for (size_t i = 0; i < s->slots.size(); ++i) {
+        s->slots[i]->stream = s->streams[i % c.n_streams];
+        s->slots[i]->group = s->stream_group[i % c.n_streams];
+    }
+    // with results that include counts and every stream on one copy engine,
+    // downloads go by host stores so that they overlap the engine's uploads
+    if (c.flags & GRIM_SERVE_STORE_DOWNLOADS)
+        s->store_downloads = true;
+    else if (c.flags & GRIM_SERVE_ENGINE_DOWNLOADS)
+        s->store_downloads = false;
+    else
+        s->store_downloads = s->n_groups < 2 && !bits_only && c.n_streams > 1;
     grim_server *raw = s.release();
     for (auto &sl : raw->slots) {
         Slot *p = sl.get();
@@ -1191,6 +1315,7 @@ extern "C" int grim_serve_submit(grim_server_t *s, const grim_batch_t *b, uint64
             r->host = s->arena + off;
             r->arena_off = off;
             r->pinned = true;
+            r->counts_writable = true;  // the arena is page-locked
         }
     }
     if (!r->host) {
@@ -1233,6 +1358,7 @@ extern "C" int grim_serve_submit_inplace(grim_server_t *s, const grim_batch_t *b
         return GRIM_E_INVALID;
     auto r = std::make_shared<Request>();
     r->in_place = true;
+    r->counts_writable = counts && backend().device_writable(counts);
     r->p_words = b->reads_2bit;
     r->p_read_off = b->read_off;
     r->p_read_len = b->read_len;
@@ -1384,6 +1510,7 @@ extern "C" int grim_serve_stats(grim_server_t *s, grim_serve_stats_t *out, int r
     out->peak_device_bytes = s->peak_bytes;
     out->mean_requests_per_tick = s->ticks ? (double)s->reqs_in_ticks / s->ticks : 0.0;
     out->sched_admit_s = s->admit_s;
+    out->stream_groups = s->n_groups;
     out->sched_launch_s = s->launch_s;
     out->sched_retire_s = s->retire_s;
     if (reset) {

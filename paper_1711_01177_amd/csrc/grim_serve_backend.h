@@ -38,6 +38,10 @@ struct Backend {
     virtual int stream_sync(void *s) const = 0;
     virtual int copy_h2d(void *dst, const void *src, uint64_t bytes, void *s) const = 0;
     virtual int copy_d2h(void *dst, const void *src, uint64_t bytes, void *s) const = 0;
+    // copy_d2h done by the device's compute units storing into host memory
+    // (no copy engine); dst must be memory for which device_writable holds
+    virtual int store_d2h(void *dst, const void *src, uint64_t bytes, void *s) const = 0;
+    virtual bool device_writable(const void *p) const = 0;
     virtual int notify(void *s, void (*fn)(void *), void *arg) const = 0;
     // the filter (grim_filter_batch) and the workspace it needs
     virtual int filter(const grim_index_t *idx, const grim_batch_t *b, int32_t *counts,

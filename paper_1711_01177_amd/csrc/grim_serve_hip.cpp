@@ -4,6 +4,7 @@
 // queued on the stream.
 #include <hip/hip_runtime.h>
 
+#include "grim_internal.h"
 #include "grim_serve_backend.h"
 
 namespace {
@@ -71,6 +72,22 @@ struct HipBackend final : grim_serve::Backend {
                               static_cast<hipStream_t>(s)) == hipSuccess
                    ? GRIM_OK
                    : GRIM_E_HIP;
+    }
+    int store_d2h(void *dst, const void *src, uint64_t bytes, void *s) const override
+    {
+        return grim::launch_copy_to_host(static_cast<hipStream_t>(s), dst, src, bytes) ==
+                       hipSuccess
+                   ? GRIM_OK
+                   : GRIM_E_HIP;
+    }
+    bool device_writable(const void *p) const override
+    {
+        hipPointerAttribute_t a;
+        if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+            (void)hipGetLastError();  // pageable memory: clear the error
+            return false;
+        }
+        return a.type == hipMemoryTypeHost;
     }
     int notify(void *s, void (*fn)(void *), void *arg) const override
     {

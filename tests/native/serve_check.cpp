@@ -296,6 +296,11 @@ void refusals(grim_index_t *idx)
     bad = cfg;
     bad.n_streams = 17;
     CHECK(grim_serve_create(idx, &bad, &srv) == GRIM_E_INVALID);
+    bad = cfg;
+    bad.flags = GRIM_SERVE_STORE_DOWNLOADS | GRIM_SERVE_ENGINE_DOWNLOADS;
+    CHECK(grim_serve_create(idx, &bad, &srv) == GRIM_E_INVALID);
+    bad.flags = 8;
+    CHECK(grim_serve_create(idx, &bad, &srv) == GRIM_E_INVALID);
     std::printf("refusals: ok\n");
 }
 
@@ -359,7 +364,7 @@ int main()
     wide.bad_every = 5;
     run(wide, idx, 5);
     Scenario big = cancels;
-    big.name = "large requests: slices moved by DMA, split over three streams, three ticks each";
+    big.name = "large requests: slices moved by DMA, downloads by host stores, split over three streams, three ticks each";
     big.cfg.ticks_per_stream = 3;
     big.cfg.max_tick_pairs = 100000;
     big.cfg.hbm_budget_bytes = 64ull << 20;
@@ -367,6 +372,7 @@ int main()
     big.per_thread = 5;
     big.max_reads = 3000;
     big.bad_every = 4;
+    big.cfg.flags = GRIM_SERVE_STORE_DOWNLOADS;
     run(big, idx, 6);
     refusals(idx);
     destroy_with_work_queued(idx);

@@ -142,6 +142,11 @@ struct FakeBackend final : grim_serve::Backend {
         static_cast<Stream *>(s)->push([=] { std::memcpy(dst, src, bytes); });
         return GRIM_OK;
     }
+    int store_d2h(void *dst, const void *src, uint64_t bytes, void *s) const override
+    {
+        return copy_d2h(dst, src, bytes, s);
+    }
+    bool device_writable(const void *) const override { return true; }
     int notify(void *s, void (*fn)(void *), void *arg) const override
     {
         static_cast<Stream *>(s)->push([=] { fn(arg); });

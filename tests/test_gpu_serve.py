@@ -103,8 +103,19 @@ def test_alone_vs_mix(setup):
         assert rc == 0, (i, rc)
         assert np.array_equal(c, solo[i][1]), f"request {i}: counts differ in the mix"
         assert np.array_equal(b, solo[i][2]), f"request {i}: pass bits differ in the mix"
-    s = srv.stats()
+    s = srv.stats(reset=True)
     say("serve stats", s)
+    assert s["completed"] == len(reqs)
+    assert s["peak_device_bytes"] <= 256 << 20
+    # the same requests submitted at once: they queue, so ticks fuse several
+    tickets = [srv.submit(hb) for _, hb in reqs]
+    for i, t in enumerate(tickets):
+        rc, c, b, st = srv.wait(t)
+        assert rc == 0, (i, rc)
+        assert np.array_equal(c, solo[i][1]), f"request {i}: counts differ in the burst"
+        assert np.array_equal(b, solo[i][2]), f"request {i}: pass bits differ in the burst"
+    s = srv.stats()
+    say("burst stats", s)
     assert s["completed"] == len(reqs)
     assert s["ticks"] < len(reqs), "no request was fused with another"
     assert s["peak_device_bytes"] <= 256 << 20
@@ -241,8 +252,9 @@ def test_inplace_submission_matches_alone(setup):
 
 def test_pageable_inplace_submission(setup):
     """In-place requests in pageable memory (staged by the runtime), alone and
-    in ticks mixed with pinned ones: every request equals its solo run and its
-    counts land in the caller's buffer."""
+    in ticks mixed with pinned ones, results downloaded by the copy engine or
+    (pinned buffers only) stored by a kernel: every request equals its solo run
+    and its counts land in the caller's buffer."""
     g, w, idx = setup
     reqs = make_requests(g, w, 18, 19, max_reads=800)
     solo = [alone(g, idx, sub) for sub, _ in reqs]
@@ -252,9 +264,11 @@ def test_pageable_inplace_submission(setup):
     pinned = [g.HostBatch(sub["codes"], sub["read_off"], sub["read_len"], sub["read_e"],
                           sub["e_den"], sub["cand_off"], sub["cand_bin"], max_len=256, pinned=True)
               for sub, _ in reqs]
-    for name, batches in (("pageable", pageable), ("pinned", pinned),
-                          ("mixed", [pageable[i] if i % 2 else pinned[i] for i in range(len(reqs))])):
-        srv = g.Server(idx, hbm_budget_bytes=64 << 20, max_inflight=8, n_streams=2, max_len=256)
+    mixed = [pageable[i] if i % 2 else pinned[i] for i in range(len(reqs))]
+    for name, batches, downloads in (("pageable", pageable, "auto"), ("pinned", pinned, "auto"),
+                                     ("mixed", mixed, "auto"), ("mixed, stored", mixed, "store")):
+        srv = g.Server(idx, hbm_budget_bytes=64 << 20, max_inflight=8, n_streams=2, max_len=256,
+                       downloads=downloads)
         ts = [srv.submit_inplace(hb) for hb in batches]
         for i, t in enumerate(ts):
             rc, c, b, st = srv.wait(t)
@@ -359,17 +373,20 @@ def test_cancel_request_running_in_parts(setup):
     srv.destroy()
 
 
-@pytest.mark.parametrize("ticks_per_stream,bits_only", [(1, False), (2, False), (3, True), (0, True)])
-def test_scheduling_policies_match_oracle(setup, ticks_per_stream, bits_only):
+@pytest.mark.parametrize("ticks_per_stream,bits_only,downloads",
+                         [(1, False, "auto"), (1, False, "store"), (2, False, "engine"),
+                          (2, False, "store"), (3, True, "auto"), (0, True, "store")])
+def test_scheduling_policies_match_oracle(setup, ticks_per_stream, bits_only, downloads):
     """One request mix through every scheduling policy: one to three ticks per
     stream, with upload turns (counts and pass bits) and without (pass bits
-    only), ticks small enough that requests run in parts; every request's
-    results against the oracle."""
+    only), results downloaded by the copy engine or stored by a kernel, ticks
+    small enough that requests run in parts; every request's results against
+    the oracle."""
     g, w, idx = setup
     reqs = make_requests(g, w, 40, 17 + ticks_per_stream, max_reads=3000)
     srv = g.Server(idx, hbm_budget_bytes=128 << 20, max_inflight=32, n_streams=3,
-                   max_tick_pairs=50_000, max_len=256, pass_bits_only=bits_only,
-                   ticks_per_stream=ticks_per_stream)
+                   max_tick_pairs=80_000, max_len=256, pass_bits_only=bits_only,
+                   ticks_per_stream=ticks_per_stream, downloads=downloads)
     try:
         tickets = [srv.submit(hb) for _, hb in reqs]
         for i, ((sub, hb), t) in enumerate(zip(reqs, tickets)):
