@@ -273,6 +273,7 @@ def serving_leg(g, idx, w, rng, loads=(0.25, 0.5, 0.75, 0.9), n_requests=10_000,
                capacity_ticks=cap_stats["ticks"],
                capacity_worker_busy=worker_busy,
                capacity_admission_busy=admit_busy,
+               stream_groups=cap_stats["stream_groups"],
                results_checked=checked,
                link_bytes_per_pair=dict(up=up_bytes / n_pairs_all, down=down_bytes / n_pairs_all),
                points=[])
