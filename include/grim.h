@@ -87,9 +87,18 @@ int grim_max_edits(uint32_t L, uint32_t e_num, uint32_t e_den, uint32_t *E);
 int grim_threshold(uint32_t L, uint32_t q, uint32_t E, int64_t *T);
 
 /* ------------------------------------------------------------------- index */
+/* Build kernels (grim_params_t.build).  Both compute the same vectors:
+ * GRIM_BUILD_BLOCKS (the token sets of whole blocks of B starts in LDS, one
+ * thread per packed word; bins whose whole blocks fit a workgroup's LDS) and
+ * GRIM_BUILD_PER_BIN (any geometry: one wavefront per bin). */
+#define GRIM_BUILD_AUTO 0u
+#define GRIM_BUILD_PER_BIN 1u
+#define GRIM_BUILD_BLOCKS 2u
+
 typedef struct grim_params {
     uint32_t q;            /* token length: 4..7 (vectors of 32 B .. 2 KiB)     */
-    uint32_t reserved;     /* must be 0                                         */
+    uint32_t build;        /* GRIM_BUILD_AUTO (BLOCKS where the geometry fits it,
+                              else PER_BIN) or one of them                     */
     uint64_t bin_stride;   /* B: bin b starts at b * B                          */
     uint64_t overlap;      /* O: bin b extends O bases past (b+1) * B           */
 } grim_params_t;
@@ -114,8 +123,10 @@ typedef struct grim_index_info {
  * layout.  The vectors are built on the current device by a HIP kernel on
  * `stream` and stay resident there; the call returns after the build has
  * finished.  The caller owns *out and releases it with grim_index_free.
- * Errors: GRIM_E_INVALID (NULL, ref_len == 0, B == 0, reserved != 0, more than
- * 2^32 - 1 bins), GRIM_E_UNSUPPORTED (q outside 4..7), GRIM_E_NOMEM, GRIM_E_HIP. */
+ * Errors: GRIM_E_INVALID (NULL, ref_len == 0, B == 0, build not one of the
+ * GRIM_BUILD_* values, more than 2^32 - 1 bins), GRIM_E_UNSUPPORTED (q outside
+ * 4..7, or a forced build kernel that does not fit the geometry),
+ * GRIM_E_NOMEM, GRIM_E_HIP. */
 int grim_build_bins(const uint32_t *ref_2bit, uint64_t ref_len, const grim_params_t *p,
                     grim_index_t **out, void *stream);
 

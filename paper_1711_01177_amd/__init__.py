@@ -48,6 +48,9 @@ GRIM_NOALLOC_SCRATCH_BYTES = 16 << 20
 GRIM_FLAG_BIN_RANGE = 1
 GRIM_FLAG_READ = 2
 GRIM_SERVE_PASS_BITS_ONLY = 1
+GRIM_BUILD_AUTO = 0
+GRIM_BUILD_PER_BIN = 1
+GRIM_BUILD_BLOCKS = 2
 GRIM_SERVE_STORE_DOWNLOADS = 2
 GRIM_SERVE_ENGINE_DOWNLOADS = 4
 GRIM_FLAG_CAND_OFF = 4
@@ -67,7 +70,7 @@ class GrimError(RuntimeError):
 
 
 class grim_params_t(ctypes.Structure):
-    _fields_ = [("q", _u32), ("reserved", _u32), ("bin_stride", _u64), ("overlap", _u64)]
+    _fields_ = [("q", _u32), ("build", _u32), ("bin_stride", _u64), ("overlap", _u64)]
 
 
 class grim_index_info_t(ctypes.Structure):
@@ -317,9 +320,11 @@ class Index:
             pass
 
 
-def grim_build_bins(ref, q, bin_stride, overlap, stream=None, packed=False, ref_len=None):
+def grim_build_bins(ref, q, bin_stride, overlap, stream=None, packed=False, ref_len=None,
+                    build=0):
     """Build the index of a reference: codes/letters (uint8), or packed words
-    (uint32, with packed=True and ref_len given)."""
+    (uint32, with packed=True and ref_len given).  build: GRIM_BUILD_* (0 = the
+    library's choice)."""
     if packed:
         words = np.ascontiguousarray(ref, dtype=np.uint32)
         n = int(ref_len)
@@ -328,7 +333,7 @@ def grim_build_bins(ref, q, bin_stride, overlap, stream=None, packed=False, ref_
     else:
         words = grim_pack_bases(ref)
         n = int(np.asarray(ref).size)
-    p = grim_params_t(int(q), 0, int(bin_stride), int(overlap))
+    p = grim_params_t(int(q), int(build), int(bin_stride), int(overlap))
     h = ctypes.c_void_p()
     _check(_lib.grim_build_bins(words.ctypes.data_as(_vp), n, ctypes.byref(p), ctypes.byref(h),
                                 _stream(stream)), "grim_build_bins")

@@ -249,7 +249,7 @@ extern "C" int grim_version(void) { return 10000; }
 extern "C" int grim_build_bins(const uint32_t *ref_2bit, uint64_t ref_len, const grim_params_t *p,
                                grim_index_t **out, void *stream)
 {
-    if (!ref_2bit || !p || !out || ref_len == 0 || p->bin_stride == 0 || p->reserved != 0)
+    if (!ref_2bit || !p || !out || ref_len == 0 || p->bin_stride == 0 || p->build > GRIM_BUILD_BLOCKS)
         return GRIM_E_INVALID;
     if (p->q < 4 || p->q > 7)
         return GRIM_E_UNSUPPORTED;
@@ -290,17 +290,27 @@ extern "C" int grim_build_bins(const uint32_t *ref_2bit, uint64_t ref_len, const
     }
     hipError_t e = hipMemcpyAsync(d_ref, ref_2bit, nw * 4, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) {
+        // the first kernel that fits the geometry, or the one asked for
         uint32_t *vec = reinterpret_cast<uint32_t *>(idx->d_vec);
-        e = launch_build_chunked(p->q, (uint32_t)cu_count(dev), s, d_ref, nw, ref_len,
-                                 p->bin_stride, p->overlap, n_bins, vec);
-        if (e == hipErrorNotSupported) {
-            (void)hipGetLastError();
+        const uint32_t cus = (uint32_t)cu_count(dev);
+        const uint32_t want = p->build;
+        e = hipErrorNotSupported;
+        if (want == GRIM_BUILD_AUTO || want == GRIM_BUILD_BLOCKS)
+            e = launch_build_chunked(p->q, cus, s, d_ref, nw, ref_len, p->bin_stride, p->overlap,
+                                     n_bins, vec);
+        if (e == hipErrorNotSupported && (want == GRIM_BUILD_AUTO || want == GRIM_BUILD_PER_BIN)) {
             uint64_t grid = (n_bins + 3) / 4;
-            const uint64_t cap = (uint64_t)cu_count(dev) * 32;
+            const uint64_t cap = (uint64_t)cus * 32;
             if (grid > cap)
                 grid = cap;
             e = launch_build(p->q, dim3((uint32_t)grid), s, d_ref, nw, ref_len, p->bin_stride,
                              p->overlap, n_bins, vec);
+        }
+        if (e == hipErrorNotSupported) {  // only a forced kernel gets here
+            (void)hipFree(d_ref);
+            (void)hipFree(idx->d_vec);
+            delete idx;
+            return GRIM_E_UNSUPPORTED;
         }
     }
     if (e == hipSuccess)

@@ -70,7 +70,7 @@ def test_unsupported_parameters(g):
     p = g.grim_params_t(5, 0, 0, 0)                   # stride 0
     assert L.grim_build_bins(words.ctypes.data_as(ctypes.c_void_p), 100, ctypes.byref(p),
                              ctypes.byref(out), None) == g.GRIM_E_INVALID
-    p = g.grim_params_t(5, 1, 200, 0)                 # reserved field set
+    p = g.grim_params_t(5, 3, 200, 0)                 # no such build kernel
     assert L.grim_build_bins(words.ctypes.data_as(ctypes.c_void_p), 100, ctypes.byref(p),
                              ctypes.byref(out), None) == g.GRIM_E_INVALID
     for k in (3, 16):

@@ -32,14 +32,32 @@ def test_index_parity_tiny(tiny):
     assert np.array_equal(idx.to_host(), orc[3])
 
 
+def build_every_kernel(g, ref, q, B, O, want):
+    """Builds the index with the library's choice and with each build kernel
+    forced; every kernel that takes the geometry must give the oracle's
+    vectors.  Returns the kernels that took it."""
+    took = []
+    for build in (g.GRIM_BUILD_AUTO, g.GRIM_BUILD_PER_BIN, g.GRIM_BUILD_BLOCKS):
+        try:
+            idx = g.grim_build_bins(ref, q, B, O, build=build)
+        except g.GrimError as e:
+            assert build != g.GRIM_BUILD_AUTO and e.code == g.GRIM_E_UNSUPPORTED, (build, e)
+            continue
+        took.append(build)
+        assert idx.n_bins == want.shape[0]
+        assert np.array_equal(idx.to_host(), want), f"build kernel {build}"
+    assert g.GRIM_BUILD_PER_BIN in took
+    return took
+
+
 @pytest.mark.parametrize("q,B,O", [(4, 97, 31), (5, 200, 105), (6, 1000, 263), (7, 333, 1)])
 def test_index_parity_params(q, B, O):
     say("index parity", q, B, O)
     ref = gs.reference(77, 250_003 if q < 7 else 60_001, 0.3, 7, 300, 0.85, 0.98)
     g = lib()
-    idx = g.grim_build_bins(ref, q, B, O)
     want = oracle.build_index(ref, B, O, q, n_threads=8)
-    assert np.array_equal(idx.to_host(), want)
+    took = build_every_kernel(g, ref, q, B, O, want)
+    assert g.GRIM_BUILD_BLOCKS in took
 
 
 # Bin geometries at the edges of the chunked build: strides below one packed
@@ -49,21 +67,24 @@ def test_index_parity_params(q, B, O):
 # the chunk's LDS (q=7 with m = 19, q=4 with m = 598), which take the
 # one-wavefront-per-bin kernel, a 100 kb stride (three bins), and a stride
 # beyond 2^31 (one bin; offsets inside a chunk would leave 32 bits, so the
-# per-bin kernel again).
+# per-bin kernel again); the batched geometry, alone and with a genome that
+# ends mid-way through a workgroup's blocks, and two more strides.  Where the
+# block kernel takes a geometry, the per-bin kernel is run on it too.
 @pytest.mark.parametrize("q,B,O,G", [(5, 10, 3, 3001), (4, 7, 100, 5003), (4, 3, 1, 1001),
                                      (5, 16, 0, 4099), (6, 1, 0, 301), (4, 200, 275, 3),
                                      (5, 1, 40, 777), (7, 5, 60, 2001), (5, 100, 4, 70_001),
                                      (7, 3, 60, 1999), (4, 1, 600, 2500), (5, 20, 4, 5000),
                                      (5, 20, 24, 5000), (6, 64, 5, 9000), (5, 16, 15, 4000),
-                                     (5, 100_000, 50, 250_003), (4, 3_000_000_000, 0, 5000)])
+                                     (5, 100_000, 50, 250_003), (4, 3_000_000_000, 0, 5000),
+                                     (5, 200, 275, 100_003), (5, 160, 4, 50_000),
+                                     (4, 240, 0, 30_011), (5, 200, 275, 16_619)])
 def test_index_parity_edges(q, B, O, G):
     say("index parity edge", q, B, O, G)
     ref = np.random.default_rng(q * 1000 + B + G).integers(0, 4, G).astype(np.uint8)
     g = lib()
-    idx = g.grim_build_bins(ref, q, B, O)
     want = oracle.build_index(ref, B, O, q, n_threads=8)
-    assert idx.n_bins == want.shape[0]
-    assert np.array_equal(idx.to_host(), want)
+    took = build_every_kernel(g, ref, q, B, O, want)
+    say("  kernels", took)
 
 
 @pytest.mark.parametrize("mode", ["batched", "plain"])
