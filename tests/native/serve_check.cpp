@@ -134,6 +134,13 @@ void run(const Scenario &sc, grim_index_t *idx, uint64_t seed)
                 const grim_batch_t b = reqs[k].batch();
                 uint64_t tk = 0;
                 int rc;
+                if (k % 4 == 1) {  // in place, in memory the device cannot reach
+                    Req &q = reqs[k];
+                    fake_mark_pageable(q.words.data(), q.words.size() * 4);
+                    fake_mark_pageable(q.cand_bin.data(), q.cand_bin.size() * 4);
+                    fake_mark_pageable(q.out_counts.data(), q.out_counts.size() * 4);
+                    fake_mark_pageable(q.out_bits.data(), q.out_bits.size() * 4);
+                }
                 if (k % 2)
                     rc = grim_serve_submit_inplace(srv, &b, bits_only ? nullptr : reqs[k].out_counts.data(),
                                                    reqs[k].out_bits.data(), &tk);
@@ -237,6 +244,7 @@ void run(const Scenario &sc, grim_index_t *idx, uint64_t seed)
     CHECK(grim_serve_wait(srv, tk, -1, c.data(), bb.data(), nullptr) == GRIM_OK);
     CHECK(std::memcmp(bb.data(), q.want_bits.data(), ((q.n_pairs + 31) / 32) * 4) == 0);
     grim_serve_destroy(srv);
+    fake_clear_pageable();  // the requests' buffers go with reqs
 }
 
 void refusals(grim_index_t *idx)
@@ -356,6 +364,15 @@ int main()
     bits.cfg.n_streams = 2;
     bits.fail_every = 7;
     run(bits, idx, 4);
+    Scenario faults_shared = faults;
+    faults_shared.name = "stored downloads, failed launches and cancellations";
+    faults_shared.cfg.flags = GRIM_SERVE_STORE_DOWNLOADS;
+    run(faults_shared, idx, 7);
+    Scenario bits_shared = bits;
+    bits_shared.name = "pass bits only, stored downloads, two ticks per stream";
+    bits_shared.cfg.flags = GRIM_SERVE_PASS_BITS_ONLY | GRIM_SERVE_STORE_DOWNLOADS;
+    bits_shared.cfg.ticks_per_stream = 2;
+    run(bits_shared, idx, 8);
     Scenario wide = base;
     wide.name = "one stream, large ticks";
     wide.cfg.n_streams = 1;

@@ -30,3 +30,8 @@ uint64_t fake_filter_calls(void);
 uint64_t fake_filter_failures(void);
 // Device bytes currently allocated through the backend (pool and nothing else).
 int64_t fake_device_bytes(void);
+// Host ranges the "device" cannot reach (pageable memory): device_writable is
+// false for them.
+void fake_mark_pageable(const void *p, uint64_t bytes);
+void fake_clear_pageable(void);
+bool fake_pageable(const void *p);

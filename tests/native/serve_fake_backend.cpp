@@ -9,6 +9,7 @@
 #include <functional>
 #include <mutex>
 #include <thread>
+#include <vector>
 
 #include "../../paper_1711_01177_amd/csrc/grim_serve_backend.h"
 #include "serve_fake.h"
@@ -146,7 +147,7 @@ struct FakeBackend final : grim_serve::Backend {
     {
         return copy_d2h(dst, src, bytes, s);
     }
-    bool device_writable(const void *) const override { return true; }
+    bool device_writable(const void *p) const override { return !fake_pageable(p); }
     int notify(void *s, void (*fn)(void *), void *arg) const override
     {
         static_cast<Stream *>(s)->push([=] { fn(arg); });
@@ -214,6 +215,34 @@ void fake_filter_host(const grim_batch_t *b, uint64_t n_bins, int32_t *counts, u
                 bits[k >> 5] |= 1u << (k & 31);
         }
     }
+}
+
+namespace {
+std::mutex g_pg_mu;
+std::vector<std::pair<uintptr_t, uintptr_t>> g_pageable;
+}  // namespace
+
+void fake_mark_pageable(const void *p, uint64_t bytes)
+{
+    if (!p || !bytes)
+        return;
+    std::lock_guard<std::mutex> lk(g_pg_mu);
+    const uintptr_t a = reinterpret_cast<uintptr_t>(p);
+    g_pageable.emplace_back(a, a + bytes);
+}
+void fake_clear_pageable(void)
+{
+    std::lock_guard<std::mutex> lk(g_pg_mu);
+    g_pageable.clear();
+}
+bool fake_pageable(const void *p)
+{
+    const uintptr_t a = reinterpret_cast<uintptr_t>(p);
+    std::lock_guard<std::mutex> lk(g_pg_mu);
+    for (const auto &r : g_pageable)
+        if (a >= r.first && a < r.second)
+            return true;
+    return false;
 }
 
 void fake_fail_filter_every(uint64_t every)
