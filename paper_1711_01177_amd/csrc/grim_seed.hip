@@ -730,6 +730,7 @@ __global__ __launch_bounds__(256) void seed_sort_long_kernel(
 // Groups of 16 lanes, one read per group: its list, list[hit_off[r] ..+
 // ucnt[r]), to the CSR candidates at out[cand_off[r] ..].
 constexpr int kCopyGroup = 16;
+constexpr int kCopyBatch = 8;
 
 __global__ __launch_bounds__(256) void seed_compact_kernel(const uint32_t *__restrict__ list,
                                                            const uint64_t *__restrict__ hit_off,
@@ -737,13 +738,44 @@ __global__ __launch_bounds__(256) void seed_compact_kernel(const uint32_t *__res
                                                            uint64_t n_reads,
                                                            uint32_t *__restrict__ out)
 {
+    // the group's next read's offsets load while this one is copied, and each
+    // lane loads kCopyBatch values before it stores any, so that a read of up
+    // to kCopyGroup * kCopyBatch bins costs one round trip
     const int sub = threadIdx.x % kCopyGroup;
     const uint64_t groups = (uint64_t)gridDim.x * (blockDim.x / kCopyGroup);
-    for (uint64_t r = (uint64_t)blockIdx.x * (blockDim.x / kCopyGroup) + threadIdx.x / kCopyGroup;
-         r < n_reads; r += groups) {
-        const uint64_t src = hit_off[r], dst = cand_off[r], n = cand_off[r + 1] - dst;
-        for (uint64_t i = sub; i < n; i += kCopyGroup)
-            out[dst + i] = list[src + i];
+    uint64_t r = (uint64_t)blockIdx.x * (blockDim.x / kCopyGroup) + threadIdx.x / kCopyGroup;
+    uint64_t src = 0, dst = 0, end = 0;
+    if (r < n_reads) {
+        src = hit_off[r];
+        dst = cand_off[r];
+        end = cand_off[r + 1];
+    }
+    for (; r < n_reads; r += groups) {
+        const uint64_t rn = r + groups;
+        uint64_t nsrc = 0, ndst = 0, nend = 0;
+        if (rn < n_reads) {
+            nsrc = hit_off[rn];
+            ndst = cand_off[rn];
+            nend = cand_off[rn + 1];
+        }
+        const uint64_t n = end - dst;
+        for (uint64_t base = 0; base < n; base += kCopyGroup * kCopyBatch) {
+            uint32_t v[kCopyBatch];
+#pragma unroll
+            for (int j = 0; j < kCopyBatch; ++j) {
+                const uint64_t i = base + j * kCopyGroup + sub;
+                v[j] = i < n ? list[src + i] : 0u;
+            }
+#pragma unroll
+            for (int j = 0; j < kCopyBatch; ++j) {
+                const uint64_t i = base + j * kCopyGroup + sub;
+                if (i < n)
+                    out[dst + i] = v[j];
+            }
+        }
+        src = nsrc;
+        dst = ndst;
+        end = nend;
     }
 }
 
