@@ -177,7 +177,8 @@ def link_probe(torch, n_bytes=256 << 20, reps=5, pairs=4):
 
 def serving_leg(g, idx, w, rng, loads=(0.25, 0.5, 0.75, 0.9), n_requests=10_000, pool=256,
                 max_reads=65536, inplace=True, tick_pairs=8 << 20, n_streams=3,
-                max_inflight=1024, fixed_rates=None, bits_only=False, expect=None):
+                max_inflight=1024, fixed_rates=None, bits_only=False, expect=None,
+                ticks_per_stream=0):
     """Served latency.  A pool of `pool` requests of log-uniform size
     (1..max_reads reads) is cut from the workload.  First the server's capacity
     is measured closed-loop (a burst of requests submitted at once); then, for
@@ -209,7 +210,8 @@ def serving_leg(g, idx, w, rng, loads=(0.25, 0.5, 0.75, 0.9), n_requests=10_000,
         spans.append((r0, r1))
     mean_pairs = float(np.mean([hb.n_pairs for hb in reqs]))
     srv = g.Server(idx, hbm_budget_bytes=4 << 30, max_inflight=max_inflight, n_streams=n_streams,
-                   max_tick_pairs=tick_pairs, max_len=256, pass_bits_only=bits_only)
+                   max_tick_pairs=tick_pairs, max_len=256, pass_bits_only=bits_only,
+                   ticks_per_stream=ticks_per_stream)
     submit = srv.submit_inplace if inplace else srv.submit
 
     def finish(rc, ticket):
@@ -235,7 +237,7 @@ def serving_leg(g, idx, w, rng, loads=(0.25, 0.5, 0.75, 0.9), n_requests=10_000,
     # host thread time during the bursts, against their wall time: the
     # workers' mean occupancy (staging, queuing, retiring) and the admission
     # thread's
-    workers = n_streams * (2 if bits_only else 1)  # the server's default ticks per stream
+    workers = n_streams * (ticks_per_stream or 2)  # 2: the server's default
     worker_busy = (cap_stats["sched_launch_s"] + cap_stats["sched_retire_s"]) / \
         max(1e-9, workers * sum(walls))
     admit_busy = cap_stats["sched_admit_s"] / max(1e-9, sum(walls))

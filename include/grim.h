@@ -421,8 +421,9 @@ void grim_graph_destroy(grim_graph_t *g);
  * the slot's stream and retires it; ticks on different streams overlap on the
  * device, and a stream's next tick waits queued behind its current one.  When
  * results include counts, ticks take turns to queue their input copies (a turn
- * ends when the tick's inputs are on the device), so that uploads run one at a
- * time and the ticks' downloads are staggered against them.  A
+ * ends when the tick's inputs are on the device; a tick takes a turn only once
+ * the ticks before it on its stream have completed), so that uploads run one
+ * at a time and the ticks' downloads are staggered against them.  A
  * request with more pairs than max_tick_pairs is cut at read boundaries into
  * parts that run as separate ticks, so that its copies and launches overlap
  * across streams.  Results are bit-identical to filtering each request alone.
@@ -463,8 +464,7 @@ typedef struct grim_serve_cfg {
     uint32_t max_len;           /* longest read accepted (0 = 1024)                 */
     uint32_t flags;             /* GRIM_SERVE_* options (0: counts and pass bits)   */
     uint32_t ticks_per_stream;  /* ticks queued on one stream at once: the next one
-                                   waits behind the current one (0 = 1, or 2 with
-                                   GRIM_SERVE_PASS_BITS_ONLY; at most 4)            */
+                                   waits behind the current one (0 = 2; at most 4) */
 } grim_serve_cfg_t;
 
 typedef struct grim_req_stats {

@@ -30,10 +30,14 @@
 //     has its inputs on the device (a notice queued behind them ends the turn),
 //     so uploads run one at a time at the link's full rate and the ticks reach
 //     their filters and result copies staggered, instead of all streams moving
-//     their data in the same direction at once;
-//   - pass bits only (the upload direction alone loaded): no turns, and two
-//     slots per stream by default, so that a stream's next tick is queued
-//     behind its current one while the host retires the tick before.
+//     their data in the same direction at once.  A tick joins the gate only
+//     once the ticks before it on its own stream have completed: its uploads
+//     would otherwise wait behind that stream's downloads while holding the
+//     turn;
+//   - pass bits only (the upload direction alone loaded): no turns.
+// Either way two slots per stream by default, so that a stream's next tick is
+// staged and queued while its current one runs and the host retires the one
+// before.
 // Uploads and downloads overlap only on streams served by different copy
 // engines, which the runtime assigns out of the server's control: at create the
 // server times candidate streams, keeps streams of both engines when it finds
@@ -304,6 +308,7 @@ struct Slot {
     grim_server *srv = nullptr;
     void *stream = nullptr;        // shared with ticks_per_stream - 1 other slots
     int group = 0;                 // the stream's copy-engine group (0 or 1)
+    uint32_t stream_idx = 0;       // index of the stream in the server's list
     uint8_t *stage = nullptr;      // pinned, stage_bytes long, mirrors the tick layout
     // guarded by the server lock; the tick fields below are written by the
     // admission thread while busy is false and belong to the worker from the
@@ -350,6 +355,12 @@ struct grim_server {
     std::mutex up_mu;
     std::condition_variable up_cv;
     uint64_t up_next = 0, up_turn = 0;
+    // ticks queued on each stream and not yet complete (with upload turns and
+    // several ticks per stream, a tick takes a turn only once its stream is
+    // free, so that its uploads never wait behind that stream's downloads
+    // while they hold the turn); guarded by up_mu
+    std::vector<uint32_t> stream_ticks;
+    void stream_tick_done(uint32_t stream_idx);
     void upload_turn_end();
 
     std::mutex mu;
@@ -390,6 +401,15 @@ struct grim_server {
     void free_block(Request &r);
 };
 
+void grim_server::stream_tick_done(uint32_t stream_idx)
+{
+    {
+        std::lock_guard<std::mutex> lk(up_mu);
+        --stream_ticks[stream_idx];
+    }
+    up_cv.notify_all();
+}
+
 void grim_server::upload_turn_end()
 {
     {
@@ -421,6 +441,8 @@ void on_upload_done(void *arg)
 void on_tick_done(void *arg)
 {
     Slot *slot = static_cast<Slot *>(arg);
+    if (slot->srv->upload_turns)
+        slot->srv->stream_tick_done(slot->stream_idx);
     {
         std::lock_guard<std::mutex> lk(slot->m);
         slot->notice = true;
@@ -627,13 +649,25 @@ void grim_server::retire(Slot &s, double t_launch)
 // false if nothing could be admitted.  Admission thread, mu held.
 bool grim_server::admit_tick()
 {
-    // a free slot, on a stream of the other copy-engine group than the last
-    // tick's when there is one, so that consecutive ticks' uploads and
-    // downloads can run at once
+    // a free slot: on a stream with no tick running first (a tick on a busy
+    // stream waits for it), then on a stream of the other copy-engine group
+    // than the last tick's, so that consecutive ticks' uploads and downloads
+    // can run at once
     Slot *slot = nullptr;
-    for (auto &sp : slots)
-        if (!sp->busy && (!slot || (slot->group == last_group && sp->group != last_group)))
+    int best = -1;
+    for (auto &sp : slots) {
+        if (sp->busy)
+            continue;
+        bool idle = true;
+        for (auto &other : slots)
+            if (other->busy && other->stream_idx == sp->stream_idx)
+                idle = false;
+        const int score = (idle ? 2 : 0) + (sp->group != last_group ? 1 : 0);
+        if (score > best) {
+            best = score;
             slot = sp.get();
+        }
+    }
     if (!slot || queue.empty())
         return false;
     // admission: requests in arrival order with the e_den of the first one
@@ -927,6 +961,8 @@ int grim_server::launch(Slot &s)
     if (upload_turns) {
         const auto t0 = Clock::now();
         std::unique_lock<std::mutex> lk(up_mu);
+        up_cv.wait(lk, [&] { return stream_ticks[s.stream_idx] == 0; });
+        ++stream_ticks[s.stream_idx];
         const uint64_t mine = up_next++;
         up_cv.wait(lk, [&] { return up_turn == mine; });
         s.turn_wait_s = secs(Clock::now() - t0);
@@ -983,8 +1019,11 @@ int grim_server::launch(Slot &s)
         if (rc == GRIM_OK && be.notify(st, on_tick_done, &s) != GRIM_OK)  // last: may run at once
             rc = GRIM_E_HIP;
     }
-    if (rc != GRIM_OK)
+    if (rc != GRIM_OK) {
         (void)be.stream_sync(st);  // the tick never completes: let what was queued finish
+        if (upload_turns)
+            stream_tick_done(s.stream_idx);
+    }
     return rc;
 }
 
@@ -1160,7 +1199,7 @@ extern "C" int grim_serve_create(const grim_index_t *idx, const grim_serve_cfg_t
         c.max_len = 1024;
     const bool bits_only = (c.flags & GRIM_SERVE_PASS_BITS_ONLY) != 0;
     if (!c.ticks_per_stream)
-        c.ticks_per_stream = bits_only ? 2 : 1;
+        c.ticks_per_stream = 2;
     const uint32_t dl_flags = GRIM_SERVE_STORE_DOWNLOADS | GRIM_SERVE_ENGINE_DOWNLOADS;
     if (c.max_len > GRIM_MAX_READ_LEN || c.n_streams > 16 || c.ticks_per_stream > 4 ||
         (c.flags & ~(GRIM_SERVE_PASS_BITS_ONLY | dl_flags)) || (c.flags & dl_flags) == dl_flags)
@@ -1212,8 +1251,10 @@ extern "C" int grim_serve_create(const grim_index_t *idx, const grim_serve_cfg_t
         free_server_parts(s.get());
         return GRIM_E_HIP;
     }
+    s->stream_ticks.assign(c.n_streams, 0);
     for (size_t i = 0; i < s->slots.size(); ++i) {
         s->slots[i]->stream = s->streams[i % c.n_streams];
+        s->slots[i]->stream_idx = (uint32_t)(i % c.n_streams);
         s->slots[i]->group = s->stream_group[i % c.n_streams];
     }
     // with results that include counts and every stream on one copy engine,
