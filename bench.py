@@ -270,6 +270,7 @@ def serving_leg(g, idx, w, rng, loads=(0.25, 0.5, 0.75, 0.9), n_requests=10_000,
                (", pass bits only" if bits_only else ""),
                pool_requests=pool, mean_pairs_per_request=mean_pairs,
                max_tick_pairs=tick_pairs, n_streams=n_streams, max_inflight=max_inflight,
+               ticks_per_stream=ticks_per_stream or 2,
                capacity_burst_s=walls,
                capacity_pairs_per_s=capacity,
                capacity_ticks=cap_stats["ticks"],
