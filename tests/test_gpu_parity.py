@@ -87,6 +87,31 @@ def test_index_parity_edges(q, B, O, G):
     say("  kernels", took)
 
 
+def test_index_parity_random_geometries():
+    """Seeded random bin geometries (q 4-7, strides 1-3000, overlaps 0-2000,
+    genomes 1-40 kb, with repeats): every build kernel that takes the geometry
+    gives the oracle's vectors."""
+    g = lib()
+    rng = np.random.default_rng(20261203)
+    kinds = {g.GRIM_BUILD_BLOCKS: 0, g.GRIM_BUILD_PER_BIN: 0}
+    for case in range(24):
+        q = int(rng.integers(4, 8))
+        B = int(rng.choice([int(rng.integers(1, 17)), int(rng.integers(17, 400)),
+                            int(rng.integers(400, 3001))]))
+        O = int(rng.choice([0, int(rng.integers(0, 64)), int(rng.integers(64, 2001))]))
+        G = int(rng.integers(1, 40_001))
+        ref = rng.integers(0, 4, G).astype(np.uint8)
+        if G > 200:  # a repeated stretch, so that bins share tokens
+            a = int(rng.integers(0, G // 2))
+            n = int(rng.integers(1, G // 4 + 1))
+            ref[a + n:a + 2 * n] = ref[a:a + n][:max(0, min(n, G - a - n))]
+        say("random geometry", case, q, B, O, G)
+        want = oracle.build_index(ref, B, O, q, n_threads=8)
+        for k in build_every_kernel(g, ref, q, B, O, want):
+            kinds[k] = kinds.get(k, 0) + 1
+    assert kinds[g.GRIM_BUILD_BLOCKS] > 0 and kinds[g.GRIM_BUILD_PER_BIN] == 24
+
+
 @pytest.mark.parametrize("mode", ["batched", "plain"])
 def test_filter_parity_tiny(tiny, mode):
     w, orc = tiny
